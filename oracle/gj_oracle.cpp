@@ -1,0 +1,629 @@
+// Graphical Join -- CPU ORACLE.  TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, obviously-correct CPU implementation of what the Graphical
+// Join hot path computes.  Only the test-suite, the smoke check and the CPU
+// baseline leg of the benchmark may load it; the product library never does.
+// It shares no code, header or table with the HIP path.
+//
+// Everything here follows the definitions, not the paper's algorithms:
+//   * the join result is the natural equi-join of the tables (Sec. 1.1); here
+//     it is enumerated by a hash-join DFS (materialize) or, for tiny inputs, by
+//     an all-combinations nested loop (brute_force);
+//   * the GFJS of Definition 1 (Sec. 1.2) is "sort the result by all columns,
+//     then run-length encode each column"; sorting is a comparator over the
+//     attribute values, ties broken by the row ids (reading A4 in the design doc);
+//   * the join size is the partition function Z of Eq. 3 (Sec. 2.2): the number
+//     of row combinations that agree on every join edge.  It is counted at the
+//     level of individual rows: down(t,r) = number of ways to complete the
+//     subtree below row r, up(t,r) = number of ways to complete everything
+//     outside that subtree; fan-out(r) = down*up is the number of result tuples
+//     that use row r.
+//   * the factor ("potential", Sec. 3.2) of a table is every distinct key tuple
+//     with its frequency, computed with std::map (group-by count).
+//   * the weighted join size W = sum over result tuples of the product of the
+//     tuple's row weights, with its gradient and central finite differences, in
+//     __float128.
+//
+// Counts are __int128 saturated at 2^120, far above the int64 range in which
+// the GPU path reports results; "overflow" means the join size is >= 2^63-1.
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <numeric>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+typedef __int128 i128;
+typedef __float128 f128;
+
+namespace {
+
+const i128 CAP = ((i128)1) << 120;
+const i128 I64MAX = (i128)INT64_MAX;
+
+i128 sadd(i128 a, i128 b) {
+  i128 s = a + b;
+  return s > CAP ? CAP : s;
+}
+i128 smul(i128 a, i128 b) {
+  if (a == 0 || b == 0) return 0;
+  if (a > CAP / b) return CAP;
+  i128 p = a * b;
+  return p > CAP ? CAP : p;
+}
+int64_t to64(i128 v) { return v >= I64MAX ? INT64_MAX : (int64_t)v; }
+
+const int MAXK = 8;
+
+}  // namespace
+
+extern "C" {
+
+// Query description handed over from Python (all host memory, borrowed).
+struct orc_query {
+  int32_t n;                   // number of tables
+  const int64_t* n_rows;       // [n]
+  const int32_t* n_keys;       // [n]
+  const int32_t* const* cols;  // cols[t*8 + c]: int32 column c of table t
+  const int32_t* parent;       // [n]; parent[0] = -1, parent[t] < t
+  const int32_t* sep_col;      // [n]; column of t equal to ...
+  const int32_t* parent_col;   // [n]; ... this column of parent[t]
+};
+
+}  // extern "C"
+
+namespace {
+
+struct State {
+  int n = 0;
+  std::vector<int64_t> N;
+  std::vector<int> K, par, sep, pcol;
+  std::vector<std::vector<const int32_t*>> col;
+  std::vector<std::vector<int>> children;
+  // row lists of table t (t >= 1) by separator value, rows ascending
+  std::vector<std::unordered_map<int32_t, std::vector<int32_t>>> by_sep;
+  // row-level counts
+  std::vector<std::vector<i128>> down, up;
+  std::vector<std::unordered_map<int32_t, i128>> sumdown, upval;
+  i128 Q = 0;
+
+  int32_t key(int t, int c, int64_t r) const { return col[t][c][r]; }
+
+  // Key columns of t in the order its factor entries are sorted: the root in
+  // declared order; any other table by its separator first, then the rest in
+  // declared order.
+  std::vector<int> canon_cols(int t) const {
+    std::vector<int> v;
+    if (t > 0) v.push_back(sep[t]);
+    for (int c = 0; c < K[t]; ++c)
+      if (t == 0 || c != sep[t]) v.push_back(c);
+    return v;
+  }
+  // Columns of t that contribute attribute values to the sort order of the
+  // result: all of the root's, and for any other table all but its separator
+  // (whose value equals a column already listed for its parent).
+  std::vector<int> sigma_cols(int t) const {
+    std::vector<int> v;
+    for (int c = 0; c < K[t]; ++c)
+      if (t == 0 || c != sep[t]) v.push_back(c);
+    return v;
+  }
+  std::vector<int32_t> canon_key(int t, int64_t r) const {
+    std::vector<int32_t> k;
+    for (int c : canon_cols(t)) k.push_back(key(t, c, r));
+    return k;
+  }
+};
+
+void load(State& s, const orc_query* q) {
+  s.n = q->n;
+  s.N.assign(q->n_rows, q->n_rows + q->n);
+  s.K.assign(q->n_keys, q->n_keys + q->n);
+  s.par.assign(q->parent, q->parent + q->n);
+  s.sep.assign(q->sep_col, q->sep_col + q->n);
+  s.pcol.assign(q->parent_col, q->parent_col + q->n);
+  s.col.resize(s.n);
+  s.children.assign(s.n, {});
+  for (int t = 0; t < s.n; ++t) {
+    for (int c = 0; c < s.K[t]; ++c) s.col[t].push_back(q->cols[t * MAXK + c]);
+    if (t > 0) s.children[s.par[t]].push_back(t);
+  }
+  s.by_sep.assign(s.n, {});
+  for (int t = 1; t < s.n; ++t)
+    for (int64_t r = 0; r < s.N[t]; ++r) s.by_sep[t][s.key(t, s.sep[t], r)].push_back((int32_t)r);
+}
+
+// Row-level counting (definition of the join size as the number of agreeing
+// row combinations, Eq. 3).  down(t,r): completions of the subtree of t given
+// row r.  up(t,r): completions of the rest of the tree given row r of t.
+void count(State& s) {
+  int n = s.n;
+  s.down.assign(n, {});
+  s.up.assign(n, {});
+  s.sumdown.assign(n, {});
+  s.upval.assign(n, {});
+  for (int t = n - 1; t >= 0; --t) {
+    s.down[t].assign(s.N[t], 0);
+    for (int64_t r = 0; r < s.N[t]; ++r) {
+      i128 d = 1;
+      for (int ch : s.children[t]) {
+        auto it = s.sumdown[ch].find(s.key(t, s.pcol[ch], r));
+        d = smul(d, it == s.sumdown[ch].end() ? 0 : it->second);
+      }
+      s.down[t][r] = d;
+    }
+    if (t > 0)
+      for (int64_t r = 0; r < s.N[t]; ++r) {
+        i128& acc = s.sumdown[t][s.key(t, s.sep[t], r)];
+        acc = sadd(acc, s.down[t][r]);
+      }
+  }
+  s.Q = 0;
+  for (int64_t r = 0; r < s.N[0]; ++r) s.Q = sadd(s.Q, s.down[0][r]);
+  s.up[0].assign(s.N[0], 1);
+  for (int t = 1; t < n; ++t) {
+    int p = s.par[t];
+    for (int64_t r = 0; r < s.N[p]; ++r) {
+      i128 term = s.up[p][r];
+      for (int sib : s.children[p]) {
+        if (sib == t) continue;
+        auto it = s.sumdown[sib].find(s.key(p, s.pcol[sib], r));
+        term = smul(term, it == s.sumdown[sib].end() ? 0 : it->second);
+      }
+      i128& acc = s.upval[t][s.key(p, s.pcol[t], r)];
+      acc = sadd(acc, term);
+    }
+    s.up[t].assign(s.N[t], 0);
+    for (int64_t r = 0; r < s.N[t]; ++r) {
+      auto it = s.upval[t].find(s.key(t, s.sep[t], r));
+      s.up[t][r] = it == s.upval[t].end() ? 0 : it->second;
+    }
+  }
+}
+
+i128 lookup(const std::unordered_map<int32_t, i128>& m, int32_t v) {
+  auto it = m.find(v);
+  return it == m.end() ? 0 : it->second;
+}
+
+// Group-by count of table t: distinct key tuples (in canonical column order)
+// -> ascending row list.  std::map orders the tuples lexicographically as
+// signed int32.
+std::map<std::vector<int32_t>, std::vector<int32_t>> group_by(const State& s, int t) {
+  std::map<std::vector<int32_t>, std::vector<int32_t>> g;
+  for (int64_t r = 0; r < s.N[t]; ++r) g[s.canon_key(t, r)].push_back((int32_t)r);
+  return g;
+}
+
+// Sort key of a result tuple: attribute values in result-column order, then
+// the row ids in table order.
+std::vector<int64_t> tuple_sort_key(const State& s, const int32_t* rows) {
+  std::vector<int64_t> k;
+  for (int t = 0; t < s.n; ++t)
+    for (int c : s.sigma_cols(t)) k.push_back(s.key(t, c, rows[t]));
+  for (int t = 0; t < s.n; ++t) k.push_back(rows[t]);
+  return k;
+}
+
+struct Emitter {
+  int32_t* out;
+  int64_t limit, count = 0;
+  int n;
+  bool emit(const std::vector<int32_t>& rows) {
+    if (count >= limit) return false;
+    if (out)
+      for (int t = 0; t < n; ++t) out[count * n + t] = rows[t];
+    ++count;
+    return count < limit;
+  }
+};
+
+// Hash-join DFS in table order: the rows of t that agree with the chosen row of
+// its parent on the separator.
+bool dfs(const State& s, int t, std::vector<int32_t>& rows, Emitter& em) {
+  if (t == s.n) return em.emit(rows);
+  if (t == 0) {
+    for (int64_t r = 0; r < s.N[0]; ++r) {
+      rows[0] = (int32_t)r;
+      if (!dfs(s, 1, rows, em)) return false;
+    }
+    return true;
+  }
+  auto it = s.by_sep[t].find(s.key(s.par[t], s.pcol[t], rows[s.par[t]]));
+  if (it == s.by_sep[t].end()) return true;
+  for (int32_t r : it->second) {
+    rows[t] = r;
+    if (!dfs(s, t + 1, rows, em)) return false;
+  }
+  return true;
+}
+
+// Candidate entries of table t below the chosen prefix: rows whose separator
+// matches the parent's chosen row, grouped by key tuple (canonical order).
+std::map<std::vector<int32_t>, std::vector<int32_t>> candidates(const State& s, int t,
+                                                                 const std::vector<int32_t>& rep) {
+  std::map<std::vector<int32_t>, std::vector<int32_t>> g;
+  if (t == 0) return group_by(s, 0);
+  auto it = s.by_sep[t].find(s.key(s.par[t], s.pcol[t], rep[s.par[t]]));
+  if (it == s.by_sep[t].end()) return g;
+  for (int32_t r : it->second) g[s.canon_key(t, r)].push_back(r);
+  return g;
+}
+
+// Number of result tuples whose value groups for tables 0..t are fixed to
+// `groups` (rep[i] is any row of group i): the product of the group sizes,
+// times the completions of every subtree hanging below the fixed tables.
+i128 prefix_count(const State& s, int t, const std::vector<int64_t>& gsize, const std::vector<int32_t>& rep) {
+  i128 c = 1;
+  for (int i = 0; i <= t; ++i) c = smul(c, gsize[i]);
+  c = smul(c, s.down[t][rep[t]]);  // children of t
+  for (int j = t + 1; j < s.n; ++j) {
+    int p = s.par[j];
+    if (p < t) c = smul(c, lookup(s.sumdown[j], s.key(p, s.pcol[j], rep[p])));
+  }
+  return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+void* orc_open(const orc_query* q) {
+  State* s = new State();
+  load(*s, q);
+  count(*s);
+  return s;
+}
+void orc_close(void* h) { delete (State*)h; }
+
+// Join size; returns 0, or 3 when it does not fit below 2^63-1 (overflow).
+int orc_join_size(void* h, int64_t* out) {
+  State& s = *(State*)h;
+  *out = to64(s.Q);
+  return s.Q >= I64MAX ? 3 : 0;
+}
+
+// Factor (potential) of table t: distinct key tuples in canonical entry order,
+// keys written in *declared* column order (row-major, M x K[t]), their counts,
+// first position in the grouped row list, and the grouped row list itself.
+int64_t orc_factor(void* h, int t, int32_t* keys, int64_t* cnt, int64_t* start, int32_t* perm) {
+  State& s = *(State*)h;
+  auto g = group_by(s, t);
+  std::vector<int> cc = s.canon_cols(t);
+  int64_t e = 0, pos = 0;
+  for (auto& kv : g) {
+    if (keys)
+      for (size_t i = 0; i < cc.size(); ++i) keys[e * s.K[t] + cc[i]] = kv.first[i];
+    if (cnt) cnt[e] = (int64_t)kv.second.size();
+    if (start) start[e] = pos;
+    for (int32_t r : kv.second) {
+      if (perm) perm[pos] = r;
+      ++pos;
+    }
+    ++e;
+  }
+  return e;
+}
+
+// Surviving entries of table t (frequency in the result F > 0) with
+// c = rows in the group, U = completions below (down of any of its rows),
+// D = completions outside (up), F = sum of the rows' fan-outs.
+int64_t orc_summary_table(void* h, int t, int32_t* keys, int64_t* c, int64_t* U, int64_t* D, int64_t* F) {
+  State& s = *(State*)h;
+  auto g = group_by(s, t);
+  std::vector<int> cc = s.canon_cols(t);
+  int64_t e = 0;
+  for (auto& kv : g) {
+    i128 f = 0;
+    for (int32_t r : kv.second) f = sadd(f, smul(s.down[t][r], s.up[t][r]));
+    if (f == 0) continue;
+    int32_t r0 = kv.second[0];
+    if (keys)
+      for (size_t i = 0; i < cc.size(); ++i) keys[e * s.K[t] + cc[i]] = kv.first[i];
+    if (c) c[e] = (int64_t)kv.second.size();
+    if (U) U[e] = to64(s.down[t][r0]);
+    if (D) D[e] = to64(s.up[t][r0]);
+    if (F) F[e] = to64(f);
+    ++e;
+  }
+  return e;
+}
+
+// Edge into table t >= 1: every separator value s with M(s) = completions of
+// t's subtree over rows carrying s, and D(s) = completions outside it; only
+// values with M*D > 0, ascending.
+int64_t orc_summary_edge(void* h, int t, int32_t* sv, int64_t* M, int64_t* D) {
+  State& s = *(State*)h;
+  std::map<int32_t, std::pair<i128, i128>> m;
+  for (auto& kv : s.sumdown[t]) {
+    i128 d = lookup(s.upval[t], kv.first);
+    if (kv.second > 0 && d > 0) m[kv.first] = {kv.second, d};
+  }
+  int64_t e = 0;
+  for (auto& kv : m) {
+    if (sv) sv[e] = kv.first;
+    if (M) M[e] = to64(kv.second.first);
+    if (D) D[e] = to64(kv.second.second);
+    ++e;
+  }
+  return e;
+}
+
+// Per-row fan-out of table t: number of result tuples that contain row r.
+void orc_fanouts(void* h, int t, int64_t* out) {
+  State& s = *(State*)h;
+  for (int64_t r = 0; r < s.N[t]; ++r) out[r] = to64(smul(s.down[t][r], s.up[t][r]));
+}
+
+// Join result by hash-join DFS, first `limit` tuples in DFS order
+// (lexicographic by row ids); returns the number written.
+int64_t orc_materialize(void* h, int64_t limit, int32_t* out) {
+  State& s = *(State*)h;
+  Emitter em{out, limit, 0, s.n};
+  std::vector<int32_t> rows(s.n);
+  if (limit > 0 && s.n > 0) dfs(s, 0, rows, em);
+  return em.count;
+}
+
+// Join result by an all-combinations nested loop (tiny inputs only): every
+// combination of one row per table, kept when it agrees on every edge.
+int64_t orc_brute_force(void* h, int64_t limit, int32_t* out) {
+  State& s = *(State*)h;
+  int n = s.n;
+  for (int t = 0; t < n; ++t)
+    if (s.N[t] == 0) return 0;
+  std::vector<int32_t> rows(n, 0);
+  Emitter em{out, limit, 0, n};
+  while (true) {
+    bool ok = true;
+    for (int t = 1; t < n && ok; ++t)
+      ok = s.key(t, s.sep[t], rows[t]) == s.key(s.par[t], s.pcol[t], rows[s.par[t]]);
+    if (ok && !em.emit(rows)) break;
+    int t = n - 1;
+    while (t >= 0 && ++rows[t] == s.N[t]) rows[t--] = 0;
+    if (t < 0) break;
+  }
+  return em.count;
+}
+
+// Sort result tuples (row-major, count x n) by all attribute values, then row ids.
+void orc_sort_canonical(void* h, int32_t* tuples, int64_t count) {
+  State& s = *(State*)h;
+  int n = s.n;
+  std::vector<std::vector<int64_t>> keys(count);
+  for (int64_t i = 0; i < count; ++i) keys[i] = tuple_sort_key(s, tuples + i * n);
+  std::vector<int64_t> idx(count);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return keys[a] < keys[b]; });
+  std::vector<int32_t> tmp(tuples, tuples + count * n);
+  for (int64_t i = 0; i < count; ++i)
+    for (int t = 0; t < n; ++t) tuples[i * n + t] = tmp[idx[i] * n + t];
+}
+
+// Value of result column `level` (attribute values in result-column order).
+int orc_n_levels(void* h) {
+  State& s = *(State*)h;
+  int L = 0;
+  for (int t = 0; t < s.n; ++t) L += (int)s.sigma_cols(t).size();
+  return L;
+}
+
+// The GFJS of Definition 1 over sorted tuples: for every result column i, one
+// (value, frequency) pair per run of equal values *within a run of equal
+// values of columns 0..i-1* (per distinct prefix, as the recursive generator
+// emits them).  Writes level-major into vals/freqs (capacity count per level)
+// and the run count of each level into nruns.
+void orc_gfjs(void* h, const int32_t* tuples, int64_t count, int32_t* vals, int64_t* freqs, int64_t* nruns) {
+  State& s = *(State*)h;
+  int n = s.n;
+  std::vector<std::pair<int, int>> lv;  // (table, column) per level
+  for (int t = 0; t < n; ++t)
+    for (int c : s.sigma_cols(t)) lv.push_back({t, c});
+  int L = (int)lv.size();
+  for (int i = 0; i < L; ++i) {
+    int64_t k = -1;
+    for (int64_t r = 0; r < count; ++r) {
+      bool same = r > 0;
+      for (int j = 0; j <= i && same; ++j) {
+        int32_t a = s.key(lv[j].first, lv[j].second, tuples[r * n + lv[j].first]);
+        int32_t b = s.key(lv[j].first, lv[j].second, tuples[(r - 1) * n + lv[j].first]);
+        same = a == b;
+      }
+      if (!same) {
+        ++k;
+        vals[(int64_t)i * count + k] = s.key(lv[i].first, lv[i].second, tuples[r * n + lv[i].first]);
+        freqs[(int64_t)i * count + k] = 0;
+      }
+      freqs[(int64_t)i * count + k] += 1;
+    }
+    nruns[i] = k + 1;
+  }
+}
+
+// The result tuple of rank R in the sorted result.  Walks the tables in order,
+// choosing the value group of each from the counts of the tuples below every
+// candidate; the row ids are then the mixed-radix digits of the remainder
+// (table 0 most significant).  Returns 0, or 6 if R is out of range.
+int orc_unrank(void* h, int64_t R, int32_t* tuple) {
+  State& s = *(State*)h;
+  if (R < 0 || (i128)R >= s.Q) return 6;
+  int n = s.n;
+  i128 rem = R;
+  std::vector<int32_t> rep(n);
+  std::vector<int64_t> gsize(n);
+  std::vector<std::vector<int32_t>> grows(n);
+  for (int t = 0; t < n; ++t) {
+    auto cand = candidates(s, t, rep);
+    bool found = false;
+    for (auto& kv : cand) {
+      rep[t] = kv.second[0];
+      gsize[t] = (int64_t)kv.second.size();
+      i128 c = prefix_count(s, t, gsize, rep);
+      if (rem < c) {
+        grows[t] = kv.second;
+        found = true;
+        break;
+      }
+      rem -= c;
+    }
+    if (!found) return 6;
+  }
+  for (int t = n - 1; t >= 0; --t) {
+    tuple[t] = grows[t][(int64_t)(rem % gsize[t])];
+    rem /= gsize[t];
+  }
+  return 0;
+}
+
+// Rank of a result tuple in the sorted result (inverse of orc_unrank).
+// Returns 0, or 2 if the tuple is not in the join result.
+int orc_rank(void* h, const int32_t* tuple, int64_t* R) {
+  State& s = *(State*)h;
+  int n = s.n;
+  for (int t = 1; t < n; ++t)
+    if (s.key(t, s.sep[t], tuple[t]) != s.key(s.par[t], s.pcol[t], tuple[s.par[t]])) return 2;
+  i128 rank = 0;
+  std::vector<int32_t> rep(n);
+  std::vector<int64_t> gsize(n);
+  std::vector<int64_t> pos(n);
+  for (int t = 0; t < n; ++t) {
+    auto cand = candidates(s, t, rep);
+    std::vector<int32_t> mine = s.canon_key(t, tuple[t]);
+    for (auto& kv : cand) {
+      rep[t] = kv.second[0];
+      gsize[t] = (int64_t)kv.second.size();
+      if (kv.first == mine) {
+        pos[t] = std::find(kv.second.begin(), kv.second.end(), tuple[t]) - kv.second.begin();
+        break;
+      }
+      rank += prefix_count(s, t, gsize, rep);
+    }
+  }
+  i128 rr = 0;
+  for (int t = 0; t < n; ++t) rr = rr * gsize[t] + pos[t];
+  rank += rr;
+  *R = to64(rank);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Weighted join size W = sum over result tuples of the product of their row
+// weights, and dW/dw_r, in __float128.  With all weights 1, W is the join size.
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+struct WCounts {
+  std::vector<std::vector<f128>> down, up;
+  std::vector<std::unordered_map<int32_t, f128>> sum, upv;
+  f128 W = 0;
+};
+
+f128 wlook(const std::unordered_map<int32_t, f128>& m, int32_t v) {
+  auto it = m.find(v);
+  return it == m.end() ? 0 : it->second;
+}
+
+// down(t,r) = w_r * prod over children of the summed weights of the matching
+// subtrees; W = sum over root rows.  `w` holds per-table weight arrays.
+void wcount(const State& s, const std::vector<std::vector<f128>>& w, WCounts& o, bool with_up) {
+  int n = s.n;
+  o.down.assign(n, {});
+  o.sum.assign(n, {});
+  for (int t = n - 1; t >= 0; --t) {
+    o.down[t].assign(s.N[t], 0);
+    for (int64_t r = 0; r < s.N[t]; ++r) {
+      f128 d = w[t][r];
+      for (int ch : s.children[t]) d *= wlook(o.sum[ch], s.key(t, s.pcol[ch], r));
+      o.down[t][r] = d;
+    }
+    if (t > 0)
+      for (int64_t r = 0; r < s.N[t]; ++r) o.sum[t][s.key(t, s.sep[t], r)] += o.down[t][r];
+  }
+  o.W = 0;
+  for (int64_t r = 0; r < s.N[0]; ++r) o.W += o.down[0][r];
+  if (!with_up) return;
+  o.up.assign(n, {});
+  o.upv.assign(n, {});
+  o.up[0].assign(s.N[0], 1);
+  for (int t = 1; t < n; ++t) {
+    int p = s.par[t];
+    for (int64_t r = 0; r < s.N[p]; ++r) {
+      f128 term = o.up[p][r] * w[p][r];
+      for (int sib : s.children[p])
+        if (sib != t) term *= wlook(o.sum[sib], s.key(p, s.pcol[sib], r));
+      o.upv[t][s.key(p, s.pcol[t], r)] += term;
+    }
+    o.up[t].assign(s.N[t], 0);
+    for (int64_t r = 0; r < s.N[t]; ++r) o.up[t][r] = wlook(o.upv[t], s.key(t, s.sep[t], r));
+  }
+}
+
+std::vector<std::vector<f128>> wload(const State& s, const double* const* w) {
+  std::vector<std::vector<f128>> v(s.n);
+  for (int t = 0; t < s.n; ++t) {
+    v[t].resize(s.N[t]);
+    for (int64_t r = 0; r < s.N[t]; ++r) v[t][r] = w ? (f128)w[t][r] : (f128)1;
+  }
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+// W and every dW/dw_r (rounded to double).  grad[t] may be NULL to skip a table.
+double orc_weighted(void* h, const double* const* w, double* const* grad) {
+  State& s = *(State*)h;
+  auto wv = wload(s, w);
+  WCounts o;
+  wcount(s, wv, o, grad != nullptr);
+  if (grad)
+    for (int t = 0; t < s.n; ++t) {
+      if (!grad[t]) continue;
+      for (int64_t r = 0; r < s.N[t]; ++r) {
+        f128 below = 1;  // product of the children's summed weights
+        for (int ch : s.children[t]) below *= wlook(o.sum[ch], s.key(t, s.pcol[ch], r));
+        grad[t][r] = (double)(below * o.up[t][r]);
+      }
+    }
+  return (double)o.W;
+}
+
+// Central finite differences (W(w + h e_r) - W(w - h e_r)) / (2h) with
+// h = hfrac * w_r, each W recomputed from scratch in __float128, for the rows
+// `rows` of table t.  W is multilinear in each weight, so the difference
+// quotient has no truncation error.  Runs on `threads` CPU threads.
+void orc_weighted_fd(void* h, const double* const* w, int t, const int64_t* rows, int64_t nrows,
+                     double hfrac, int threads, double* out) {
+  State& s = *(State*)h;
+  auto base = wload(s, w);
+  if (threads < 1) threads = 1;
+  auto work = [&](int tid) {
+    auto wv = base;
+    WCounts o;
+    for (int64_t i = tid; i < nrows; i += threads) {
+      int64_t r = rows[i];
+      f128 w0 = base[t][r];
+      f128 hh = (f128)hfrac * w0;
+      wv[t][r] = w0 + hh;
+      wcount(s, wv, o, false);
+      f128 wp = o.W;
+      wv[t][r] = w0 - hh;
+      wcount(s, wv, o, false);
+      f128 wm = o.W;
+      wv[t][r] = w0;
+      out[i] = (double)((wp - wm) / (2 * hh));
+    }
+  };
+  std::vector<std::thread> th;
+  for (int i = 0; i < threads; ++i) th.emplace_back(work, i);
+  for (auto& x : th) x.join();
+}
+
+}  // extern "C"

@@ -1,0 +1,228 @@
+"""ctypes wrapper over the CPU oracle (``liboracle.so``).  TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  It never touches the HIP library and the HIP library
+never touches it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "gj_oracle.cpp")
+MAXK = 8
+
+OVERFLOW = 3
+RANGE = 6
+NOT_IN_RESULT = 2
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (host only; no HIP headers)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", SRC, "-o", LIB + ".tmp"]
+        subprocess.check_call(cmd)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class _Q(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_rows", C.c_void_p), ("n_keys", C.c_void_p),
+                ("cols", C.c_void_p), ("parent", C.c_void_p), ("sep_col", C.c_void_p),
+                ("parent_col", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.orc_open.restype = vp
+        L.orc_open.argtypes = [vp]
+        L.orc_close.argtypes = [vp]
+        L.orc_join_size.argtypes = [vp, vp]
+        L.orc_join_size.restype = C.c_int
+        L.orc_factor.argtypes = [vp, C.c_int, vp, vp, vp, vp]
+        L.orc_factor.restype = i64
+        L.orc_summary_table.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
+        L.orc_summary_table.restype = i64
+        L.orc_summary_edge.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.orc_summary_edge.restype = i64
+        L.orc_fanouts.argtypes = [vp, C.c_int, vp]
+        L.orc_materialize.argtypes = [vp, i64, vp]
+        L.orc_materialize.restype = i64
+        L.orc_brute_force.argtypes = [vp, i64, vp]
+        L.orc_brute_force.restype = i64
+        L.orc_sort_canonical.argtypes = [vp, vp, i64]
+        L.orc_n_levels.argtypes = [vp]
+        L.orc_n_levels.restype = C.c_int
+        L.orc_gfjs.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.orc_unrank.argtypes = [vp, i64, vp]
+        L.orc_unrank.restype = C.c_int
+        L.orc_rank.argtypes = [vp, vp, vp]
+        L.orc_rank.restype = C.c_int
+        L.orc_weighted.argtypes = [vp, vp, vp]
+        L.orc_weighted.restype = C.c_double
+        L.orc_weighted_fd.argtypes = [vp, vp, C.c_int, vp, i64, C.c_double, C.c_int, vp]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Oracle:
+    """Row-level reference for one query (see gj_oracle.cpp for definitions)."""
+
+    def __init__(self, q):
+        self.q = q
+        n = q.n_tables
+        self._cols = [[np.ascontiguousarray(c, dtype=np.int32) for c in tb] for tb in q.tables]
+        self._nrows = np.array([q.n_rows(t) for t in range(n)], dtype=np.int64)
+        self._nkeys = np.array([len(tb) for tb in q.tables], dtype=np.int32)
+        ptrs = np.zeros(n * MAXK, dtype=np.uint64)
+        for t in range(n):
+            for c, col in enumerate(self._cols[t]):
+                ptrs[t * MAXK + c] = col.ctypes.data
+        self._ptrs = ptrs
+        self._par = np.array(q.parent, dtype=np.int32)
+        self._sep = np.array(q.sep_col, dtype=np.int32)
+        self._pcol = np.array(q.parent_col, dtype=np.int32)
+        self._qs = _Q(n, self._nrows.ctypes.data, self._nkeys.ctypes.data, ptrs.ctypes.data,
+                      self._par.ctypes.data, self._sep.ctypes.data, self._pcol.ctypes.data)
+        self.h = lib().orc_open(C.byref(self._qs))
+
+    def close(self):
+        if self.h:
+            lib().orc_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n(self):
+        return self.q.n_tables
+
+    def join_size(self):
+        """(|Q|, overflow flag)."""
+        out = np.zeros(1, dtype=np.int64)
+        rc = lib().orc_join_size(self.h, _p(out))
+        return int(out[0]), rc == OVERFLOW
+
+    def factor(self, t):
+        N = self.q.n_rows(t)
+        k = len(self.q.tables[t])
+        keys = np.zeros((max(N, 1), k), dtype=np.int32)
+        cnt = np.zeros(max(N, 1), dtype=np.int64)
+        start = np.zeros(max(N, 1), dtype=np.int64)
+        perm = np.zeros(max(N, 1), dtype=np.int32)
+        M = lib().orc_factor(self.h, t, _p(keys), _p(cnt), _p(start), _p(perm))
+        return dict(keys=keys[:M], count=cnt[:M], start=start[:M], perm=perm[:N])
+
+    def summary_table(self, t):
+        N = self.q.n_rows(t)
+        k = len(self.q.tables[t])
+        cap = max(N, 1)
+        keys = np.zeros((cap, k), dtype=np.int32)
+        arrs = [np.zeros(cap, dtype=np.int64) for _ in range(4)]
+        m = lib().orc_summary_table(self.h, t, _p(keys), *[_p(a) for a in arrs])
+        return dict(keys=keys[:m], c=arrs[0][:m], U=arrs[1][:m], D=arrs[2][:m], F=arrs[3][:m])
+
+    def summary_edge(self, t):
+        N = self.q.n_rows(t)
+        cap = max(N, 1)
+        s = np.zeros(cap, dtype=np.int32)
+        M = np.zeros(cap, dtype=np.int64)
+        D = np.zeros(cap, dtype=np.int64)
+        m = lib().orc_summary_edge(self.h, t, _p(s), _p(M), _p(D))
+        return dict(s=s[:m], M=M[:m], D=D[:m])
+
+    def fanouts(self, t):
+        out = np.zeros(max(self.q.n_rows(t), 1), dtype=np.int64)
+        lib().orc_fanouts(self.h, t, _p(out))
+        return out[: self.q.n_rows(t)]
+
+    def materialize(self, limit=None):
+        if limit is None:
+            limit = self.join_size()[0]
+        out = np.zeros((max(limit, 1), self.n), dtype=np.int32)
+        m = lib().orc_materialize(self.h, int(limit), _p(out))
+        return out[:m]
+
+    def brute_force(self, limit=10**7):
+        out = np.zeros((limit, self.n), dtype=np.int32)
+        m = lib().orc_brute_force(self.h, int(limit), _p(out))
+        return out[:m]
+
+    def sort_canonical(self, tuples):
+        t = np.ascontiguousarray(tuples, dtype=np.int32).copy()
+        lib().orc_sort_canonical(self.h, _p(t), int(t.shape[0]))
+        return t
+
+    def canonical_result(self):
+        return self.sort_canonical(self.materialize())
+
+    def gfjs(self, sorted_tuples):
+        """Per result column: list of (value, freq) runs (Definition 1 per prefix)."""
+        st = np.ascontiguousarray(sorted_tuples, dtype=np.int32)
+        L = lib().orc_n_levels(self.h)
+        cnt = st.shape[0]
+        vals = np.zeros((L, max(cnt, 1)), dtype=np.int32)
+        freqs = np.zeros((L, max(cnt, 1)), dtype=np.int64)
+        nr = np.zeros(L, dtype=np.int64)
+        lib().orc_gfjs(self.h, _p(st), cnt, _p(vals), _p(freqs), _p(nr))
+        return [(vals[i, : nr[i]].copy(), freqs[i, : nr[i]].copy()) for i in range(L)]
+
+    def unrank(self, R):
+        out = np.zeros(self.n, dtype=np.int32)
+        rc = lib().orc_unrank(self.h, int(R), _p(out))
+        if rc != 0:
+            raise IndexError(R)
+        return out
+
+    def rank(self, tup):
+        t = np.ascontiguousarray(tup, dtype=np.int32)
+        out = np.zeros(1, dtype=np.int64)
+        rc = lib().orc_rank(self.h, _p(t), _p(out))
+        if rc != 0:
+            raise ValueError("tuple is not in the join result")
+        return int(out[0])
+
+    def _wptrs(self, w):
+        if w is None:
+            return None, None
+        ws = [np.ascontiguousarray(x, dtype=np.float64) for x in w]
+        ptrs = np.array([x.ctypes.data for x in ws], dtype=np.uint64)
+        return ws, ptrs
+
+    def weighted(self, w=None, grads=True):
+        """(W, [dW/dw per table]) in __float128, rounded to float64."""
+        ws, ptrs = self._wptrs(w)
+        g = [np.zeros(max(self.q.n_rows(t), 1)) for t in range(self.n)] if grads else None
+        gp = np.array([x.ctypes.data for x in g], dtype=np.uint64) if grads else None
+        W = lib().orc_weighted(self.h, _p(ptrs) if ptrs is not None else None,
+                               _p(gp) if gp is not None else None)
+        return W, ([x[: self.q.n_rows(t)] for t, x in enumerate(g)] if grads else None)
+
+    def weighted_fd(self, w, t, rows, hfrac=0.25, threads=1):
+        ws, ptrs = self._wptrs(w)
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        out = np.zeros(len(rows))
+        lib().orc_weighted_fd(self.h, _p(ptrs), int(t), _p(rows), len(rows), float(hfrac),
+                              int(threads), _p(out))
+        return out
