@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the Graphical Join hot path on one MI355X.
+
+A step is one pass of the whole path over one batch of synthetic input that
+is already resident in HBM: factor build for every table, summary (upward and
+downward passes, compaction), then desummarization of a fixed number of
+2^28-tuple chunks of the sorted result as int64 row-id tuples.
+
+Default workload: 4-table chain T1(A,B)-T2(B,C)-T3(C,D)-T4(D,E), 10^7 rows per
+table, int32 keys Zipf(1.1) over 10^5 values (independent permutation per
+column), two int32 payload columns per table (resident, not read).  The join
+size is about 2e12; 16 chunks (4.3e9 tuples, 137 GB of row ids) are written
+per step.
+
+Prints one JSON line.  `value` = tuples materialized per second of whole-step
+time; the roofline object is for the expansion kernel (HIP events around each
+launch on the stream the kernel runs on).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+CHUNK = 1 << 28
+
+
+def _workload(name: str):
+    from paper_2206_10435_amd import workloads as W
+
+    if name == "chain4":
+        return W.cfg2(), "chain4_N1e7_D1e5_zipf1.1_payload2"
+    if name == "chain3":
+        return W.cfg1(), "chain3_N1e4_D1e3_uniform"
+    if name == "star":
+        return W.cfg3(), "star_plus_chain_F5e7"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def _traffic(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        import hashlib
+
+        src = open(os.path.join(ROOT, "paper_2206_10435_amd", "csrc", rec["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+            return None
+        return rec["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def cpu_baseline(q, tuples: int):
+    """The oracle as it stands (single thread): hash build + row-level counting
+    of the full tables, then hash-join materialization of the first `tuples`
+    result tuples."""
+    from oracle import oracle as O
+
+    O.build()
+    t0 = time.perf_counter()
+    o = O.Oracle(q)
+    t1 = time.perf_counter()
+    res = o.materialize(limit=tuples)
+    t2 = time.perf_counter()
+    n = len(res)
+    del res
+    o.close()
+    return {
+        "value": n / (t2 - t0),
+        "unit": "tuples/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"full input tables; hash build + counting ({t1 - t0:.2f} s) then the first {n} "
+                  f"result tuples by hash-join DFS ({t2 - t1:.2f} s)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="chain4")
+    ap.add_argument("--chunks", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-tuples", type=int, default=100_000_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this benchmark runs on exactly one GPU: the path is single-GPU "
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2206_10435_amd import gj
+
+    q, wname = _workload(args.workload)
+    n = q.n_tables
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    tabs = gj.to_device_tables(q)
+    payload = [[torch.from_numpy(c).to(dev) for c in p] for p in q.payload]  # resident, unread
+    ctx = gj.Context(0)
+    stream = torch.cuda.current_stream()
+    total_rows = q.total_rows()
+
+    # sizes
+    f = ctx.build_factors(tabs, q.parent, q.sep_col, q.parent_col)
+    s = ctx.summarize(f)
+    Q = s.join_size
+    nchunks = max(1, min(args.chunks, (Q + CHUNK - 1) // CHUNK))
+    chunk_rows = [min(CHUNK, Q - c * CHUNK) for c in range(nchunks)]
+    tuples_per_step = int(sum(chunk_rows))
+    out = torch.empty(CHUNK * n, dtype=torch.int64, device=dev)
+    del f, s
+    torch.cuda.synchronize()
+
+    exp_ms = []
+    build_s = []
+
+    def step(record: bool):
+        t0 = time.perf_counter()
+        f = ctx.build_factors(tabs, q.parent, q.sep_col, q.parent_col)
+        s = ctx.summarize(f)  # returns the join size to the host (synchronizes)
+        t1 = time.perf_counter()
+        for c, rows in enumerate(chunk_rows):
+            if record:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            ctx.desummarize(s, c * CHUNK, rows, out)
+            if record:
+                e1.record(stream)
+                exp_ms.append((e0, e1))
+        if record:
+            build_s.append(t1 - t0)
+        return s
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    value = tuples_per_step / (ms_per_step / 1000.0)
+
+    durs = [a.elapsed_time(b) for a, b in exp_ms]
+    # full chunks only, for a per-launch figure of the dominant kernel
+    full = [d for d, (i) in zip(durs, range(len(durs))) if chunk_rows[i % nchunks] == CHUNK] or durs
+    avg_ms = float(np.mean(full))
+    bytes_per_launch = CHUNK * n * 8
+    achieved = bytes_per_launch / (avg_ms / 1000.0) / 1e9
+    traffic = _traffic("expand", wname)
+    build_avg = float(np.mean(build_s))
+
+    rec = {
+        "metric": "join tuples/sec materialized + summary build rows/sec; HBM GB/s vs peak",
+        "value": value,
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {
+            "workload": wname,
+            "tables": n,
+            "rows_per_table": [q.n_rows(t) for t in range(n)],
+            "join_size": Q,
+            "chunks_per_step": nchunks,
+            "chunk_tuples": CHUNK,
+            "tuples_per_step": tuples_per_step,
+            "rowid_bytes": 8,
+        },
+        "summary_build_rows_per_s": total_rows / build_avg,
+        "summary_build_ms": build_avg * 1000.0,
+        "expand_kernel_ms": avg_ms,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(q, args.cpu_tuples)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

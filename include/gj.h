@@ -1,0 +1,246 @@
+/*
+ * gj.h -- C ABI of the Graphical Join hot path on AMD MI355X (gfx950).
+ *
+ * The library answers acyclic natural equi-join queries (Sec. 1.1 of the
+ * paper: tables T_0..T_{n-1}, already filtered, joined on equal key values)
+ * the Graphical Join way (Sec. 3):
+ *
+ *   gj_build_factors  one group-by count per table: the table's factor
+ *                     (potential, Sec. 3.2) = every distinct key tuple with
+ *                     its frequency, plus the row ids grouped by tuple.
+ *   gj_summarize      sum-product message passing over the join tree
+ *                     (Sec. 2.2 Eq. 4 / Sec. 3.3 Algorithm 2 upward, the
+ *                     generation order of Sec. 3.5 Algorithms 3-4 downward):
+ *                     the join size (Eq. 3's Z) and the run-length summary of
+ *                     the result, i.e. for every surviving factor entry its
+ *                     count c, completions below U, completions outside D and
+ *                     run length F = c*U*D.
+ *   gj_desummarize    materializes any row range of the join result, sorted
+ *                     by all attribute values (Definition 1) with row ids as
+ *                     the tie-break, as row-id tuples (Sec. 3.6).
+ *
+ * Conventions
+ *   - "device" pointers are HIP device memory on the context's device; "host"
+ *     pointers are ordinary host memory.  Every call is ordered on the
+ *     context's stream; a call that returns a host value synchronizes it.
+ *   - Inputs (key columns, weights) are borrowed for the duration of the call
+ *     only.  Factors, summaries and saved states are owned by the library and
+ *     allocated through the context's allocator; output chunks are owned by
+ *     the caller.
+ *   - Every entry point returns a gj_status; out-parameters are written only
+ *     on GJ_OK.  gj_last_error() gives a message for the calling thread.
+ *   - Join graph: table 0 is the root; for t >= 1, parent[t] < t and table t
+ *     joins its parent on  key[t][sep_col[t]] == key[parent[t]][parent_col[t]].
+ *     Composite separators and cyclic queries are rejected (GJ_E_GRAPH).
+ *   - Counts are exact int64.  If the join size is >= 2^63-1 the call reports
+ *     GJ_E_OVERFLOW (every value of the summary is bounded by the join size,
+ *     so nothing else can overflow).
+ */
+#ifndef GJ_H
+#define GJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GJ_OK = 0,
+  GJ_E_INVALID = 1,  /* bad argument (null pointer, size, key too wide to pack) */
+  GJ_E_GRAPH = 2,    /* join graph is not a rooted tree with one separator per edge */
+  GJ_E_OVERFLOW = 3, /* join size does not fit below 2^63-1 */
+  GJ_E_OOM = 4,      /* the allocator returned NULL */
+  GJ_E_DEVICE = 5,   /* a HIP runtime call failed */
+  GJ_E_RANGE = 6     /* first_row beyond the join size */
+} gj_status;
+
+#define GJ_MAX_TABLES 16 /* per query */
+#define GJ_MAX_KEYS 8    /* key columns per table */
+#define GJ_MAX_CHILDREN 8
+
+typedef struct gj_ctx gj_ctx;
+typedef struct gj_factors gj_factors;
+typedef struct gj_summary gj_summary;
+typedef struct gj_wstate gj_wstate;
+typedef struct gj_batch gj_batch;
+
+/* Device-memory allocator: returns `bytes` of device memory ordered on the
+ * context stream, or NULL.  Python passes PyTorch's caching allocator. */
+typedef void* (*gj_alloc_fn)(size_t bytes, void* user);
+typedef void (*gj_free_fn)(void* ptr, void* user);
+
+/* Context: device, stream (hipStream_t; NULL = default stream) and allocator
+ * (both NULL = hipMallocAsync/hipFreeAsync on the stream). */
+gj_status gj_ctx_create(int device, void* hip_stream, gj_alloc_fn alloc, gj_free_fn free_fn, void* user,
+                        gj_ctx** out);
+void gj_ctx_destroy(gj_ctx* ctx);
+/* Message describing the last error on the calling thread ("" if none). */
+const char* gj_last_error(void);
+
+/* One input table: n_keys int32 key columns (device pointers, SoA, n_rows each).
+ * `keys` itself is a host array of n_keys device pointers.  Only the columns
+ * that appear in the query are passed (Sec. 3.2: one node per join or output
+ * attribute); payload columns are not. */
+typedef struct {
+  int64_t n_rows;
+  int32_t n_keys; /* 1..GJ_MAX_KEYS */
+  const int32_t* const* keys;
+} gj_table;
+
+/* Join tree (Sec. 3.2, qualitative part): host arrays of n_tables entries. */
+typedef struct {
+  int32_t n_tables; /* 1..GJ_MAX_TABLES */
+  const int32_t* parent;     /* parent[0] = -1, parent[t] < t */
+  const int32_t* sep_col;    /* column of t equal to ...           (ignored for t = 0) */
+  const int32_t* parent_col; /* ... this column of parent[t]       (ignored for t = 0) */
+} gj_join_graph;
+
+/* Host-only check of a join graph against the tables' key counts: GJ_OK or
+ * GJ_E_GRAPH / GJ_E_INVALID with a message.  Runs no device code. */
+gj_status gj_validate(const gj_table* tables, const gj_join_graph* graph);
+
+/* ---- stage 1: factors (Sec. 3.2 quantitative learning: one scan per table) ----
+ * Builds every table's factor on the device.  Entries of the root are ordered
+ * by its key columns in declared order; entries of any other table by its
+ * separator column first, then its other columns in declared order; all
+ * comparisons as signed int32.  Rows inside an entry ascend by row id. */
+gj_status gj_build_factors(gj_ctx* ctx, const gj_table* tables, const gj_join_graph* graph, gj_factors** out);
+
+/* View of table t's factor (device pointers valid while the factors live):
+ *   keys[c]  int32[n_entries]  key column c (declared order) of every entry
+ *   start    int32[n_entries]  first position of the entry's rows in perm
+ *   end      int32[n_entries]  one past the last; end - start is the entry's
+ *                              frequency (the potential's count)
+ *   perm     int32[n_rows]     row ids grouped by entry, ascending inside one */
+typedef struct {
+  int64_t n_entries;
+  int64_t n_rows;
+  int32_t n_keys;
+  const int32_t* keys[GJ_MAX_KEYS];
+  const int32_t* start;
+  const int32_t* end;
+  const int32_t* perm;
+} gj_factor_view;
+gj_status gj_factor_table(const gj_factors* f, int32_t t, gj_factor_view* v);
+void gj_free_factors(gj_factors* f);
+
+/* ---- stage 2: summary (Sec. 3.3 Algorithm 2 upward; Sec. 3.5 downward) ----
+ * Upward, leaves to root (the perfect elimination order on a tree):
+ *   U_t(e) = prod over children ch of M_ch(e[parent_col[ch]]), 1 at leaves,
+ *   M_t(s) = sum over entries e of t with separator s of c_t(e) * U_t(e),
+ *   join size = sum over root entries of c_0 * U_0 (Z of Eq. 3).
+ * Downward, root to leaves (the conditioning of Algorithm 4):
+ *   D_0 = 1,  D_t(s) = sum over parent entries e' with e'[parent_col[t]] = s of
+ *   c_p(e') * D_p(e') * prod over siblings of M_sib, and F = c * U * D.
+ * Only entries with F > 0 survive (Sec. 3.3: entries of frequency < 1 are
+ * excluded, which is how unneeded intermediate results are avoided).
+ * `join_size` (host) receives the join size. */
+gj_status gj_summarize(gj_ctx* ctx, const gj_factors* f, gj_summary** out, int64_t* join_size);
+
+/* Surviving entries of table t in factor order (device pointers):
+ *   keys[c] int32, c/U/D/F int64; F = c*U*D is the entry's run length in the
+ *   result and U*D the fan-out of each of its rows.  `pre` (int64) is the
+ *   exclusive prefix sum of c*U inside the entry's separator group (over the
+ *   whole table for the root): the offset of the entry's block in the order. */
+typedef struct {
+  int64_t n_entries;
+  int32_t n_keys;
+  const int32_t* keys[GJ_MAX_KEYS];
+  const int64_t* c;
+  const int64_t* U;
+  const int64_t* D;
+  const int64_t* F;
+  const int64_t* pre;
+} gj_summary_view;
+gj_status gj_summary_table(const gj_summary* s, int32_t t, gj_summary_view* v);
+
+/* Edge into table t >= 1: separator values s (ascending, int32) with
+ * M_t(s) * D_t(s) > 0 and both messages (int64). */
+typedef struct {
+  int64_t n;
+  const int32_t* s;
+  const int64_t* M;
+  const int64_t* D;
+} gj_edge_view;
+gj_status gj_summary_edge(const gj_summary* s, int32_t t, gj_edge_view* v);
+int64_t gj_summary_join_size(const gj_summary* s);
+void gj_free_summary(gj_summary* s);
+
+/* ---- stage 3: desummarization (Sec. 3.6) ----
+ * Writes result rows [first_row, first_row + n_rows) of the sorted result
+ * (sorted by all attribute values -- the root's columns in declared order,
+ * then each further table's non-separator columns in declared order, table by
+ * table -- ties broken by the row ids (r_0, .., r_{n-1})) as row-major
+ * [n_rows x n_tables] row ids of `rowid_bytes` (4: int32, 8: int64) each into
+ * device buffer `out`.  Rows past the join size are not written; *n_written
+ * (host) receives the count.  first_row > join size -> GJ_E_RANGE. */
+gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, int64_t n_rows, int32_t rowid_bytes,
+                         void* out, int64_t* n_written);
+
+/* Paper-literal GFJS (Definition 1, as Algorithms 3-4 emit it: one run per
+ * distinct value prefix) of result rows [first_row, first_row + n_rows).
+ * Result column i (same order as above) gets runs (values[i][k],
+ * freqs[i][k]) for k < n_runs[i]; each values[i] / freqs[i] is a caller device
+ * buffer of n_rows entries (int32 / int64), n_runs a host array of
+ * gj_result_columns(s) entries. */
+int32_t gj_result_columns(const gj_summary* s);
+gj_status gj_unroll_gfjs(gj_ctx* ctx, const gj_summary* s, int64_t first_row, int64_t n_rows,
+                         int32_t* const* values, int64_t* const* freqs, int64_t* n_runs);
+
+/* ---- weighted join and its adjoint ----
+ * Every row r of table t carries a weight w_t[r]; W = sum over result tuples of
+ * the product of their rows' weights (W = join size at unit weights).  The
+ * forward pass is the upward pass with c_t(e) replaced by the summed weights
+ * of e's rows, in float64.  w[t] are device arrays of n_rows(t) weights of
+ * `w_dtype` (0: float32, 1: float64), accumulated in float64.  *d_W (device
+ * float64) receives W; *saved keeps what the backward pass needs. */
+gj_status gj_weighted_forward(gj_ctx* ctx, const gj_factors* f, const void* const* w, int32_t w_dtype, double* d_W,
+                              gj_wstate** saved);
+/* Adjoint of the forward pass (= the downward pass): grad_w[t][r] =
+ * (*d_gradW) * dW/dw_t[r] = gradW * U(e(r)) * D(e(r)), written in w_dtype into
+ * device arrays grad_w[t] (n_rows(t) each). */
+gj_status gj_weighted_backward(gj_ctx* ctx, const gj_wstate* st, const double* d_gradW, void* const* grad_w);
+void gj_free_wstate(gj_wstate* st);
+
+/* ---- batched queries ----
+ * Plans n_queries independent queries (tables of query q are
+ * tables[q_off[q] .. q_off[q+1]), graphs[q] its join tree): reads the key
+ * ranges once, sizes every workspace for the worst case, and records the
+ * whole factor build + summary of all queries as one HIP graph whose kernels
+ * each cover every query (no host synchronization, no allocation inside).
+ * tune = NULL uses built-in tile sizes. */
+typedef struct {
+  int32_t sort_items;   /* keys per thread in 64-bit radix-sort tiles (8 or 16) */
+  int32_t radix_bits;   /* digit width of the radix sort (4..8) */
+  int32_t desum_rounds; /* LDS rounds per lane of the expansion kernel (1..64) */
+  int32_t reserved;
+} gj_tune;
+gj_status gj_batch_create(gj_ctx* ctx, int32_t n_queries, const int32_t* q_off, const gj_table* tables,
+                          const gj_join_graph* graphs, const gj_tune* tune, gj_batch** out);
+/* Replays the recorded graph on `hip_stream` (NULL = context stream): recomputes
+ * every factor and summary from the (same) input columns. */
+gj_status gj_batch_launch(gj_batch* b, void* hip_stream);
+/* Same work without the graph: the kernels launched one by one (for comparison). */
+gj_status gj_batch_launch_eager(gj_batch* b, void* hip_stream);
+/* Device arrays of n_queries entries: join sizes (int64) and statuses (int32,
+ * GJ_OK or GJ_E_OVERFLOW), written by every launch. */
+const int64_t* gj_batch_join_sizes(const gj_batch* b);
+const int32_t* gj_batch_status(const gj_batch* b);
+/* Summary of query q as a borrowed gj_summary (valid until the batch is freed
+ * or relaunched; do not free it). */
+gj_status gj_batch_summary(gj_batch* b, int32_t q, const gj_summary** out);
+void gj_free_batch(gj_batch* b);
+
+/* Plumbing for bindings and tests: copies `bytes` of device memory to host
+ * memory on the context stream and waits for it. */
+gj_status gj_download(gj_ctx* ctx, void* host_dst, const void* dev_src, size_t bytes);
+
+/* Sets the default tile sizes used by later calls on this context. */
+gj_status gj_ctx_set_tune(gj_ctx* ctx, const gj_tune* tune);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GJ_H */

@@ -160,6 +160,8 @@ class Oracle:
     def materialize(self, limit=None):
         if limit is None:
             limit = self.join_size()[0]
+        if limit > 200_000_000:
+            raise MemoryError(f"refusing to materialize {limit} tuples in host memory")
         out = np.zeros((max(limit, 1), self.n), dtype=np.int32)
         m = lib().orc_materialize(self.h, int(limit), _p(out))
         return out[:m]

@@ -1,0 +1,159 @@
+// Batched queries.  Every kernel of the factor build and of the summary
+// already walks a (table, tile) work list, so a batch is one plan whose tables
+// come from many queries: each launch covers every query at once (one launch
+// per stage and tree level, not per query), and the whole sequence is
+// recorded once as a HIP graph.  Workspaces are sized by row counts only
+// (an entry count never exceeds its table's row count), so nothing inside the
+// graph allocates or waits for the host.
+#include <vector>
+
+#include "kernels.h"
+#include "plan.h"
+
+using namespace gjh;
+
+struct gj_batch {
+  gj_ctx* ctx = nullptr;
+  gj_factors* f = nullptr;
+  gj_summary* s = nullptr;  // one set of summary arrays for all queries
+  std::vector<gj_summary*> views;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  std::vector<int64_t> cnt_host;
+  bool counters_valid = false;
+};
+
+static void batch_destroy(gj_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (gj_summary* v : b->views) delete v;
+  if (b->s) {
+    b->s->borrowed = false;
+    gj_free_summary(b->s);
+  }
+  if (b->f) gj_free_factors(b->f);
+  delete b;
+}
+
+extern "C" {
+
+gj_status gj_batch_create(gj_ctx* ctx, int32_t n_queries, const int32_t* q_off, const gj_table* tables,
+                          const gj_join_graph* graphs, const gj_tune* tune, gj_batch** out) {
+  if (!ctx || n_queries < 1 || !q_off || !tables || !graphs || !out) {
+    set_error("gj_batch_create: bad argument");
+    return GJ_E_INVALID;
+  }
+  gj_tune saved = ctx->tune;
+  if (tune) {
+    gj_status st = gj_ctx_set_tune(ctx, tune);
+    if (st) return st;
+  }
+  gj_batch* b = new gj_batch();
+  b->ctx = ctx;
+  b->f = new gj_factors(ctx);
+  b->f->plan.ctx = ctx;
+  std::vector<int> qoff(q_off, q_off + n_queries + 1);
+  gj_status st = plan_tables(b->f->plan, n_queries, qoff.data(), tables, graphs);
+  if (!st) st = plan_device(b->f->plan, b->f->arena, b->f->F);
+  ctx->tune = saved;
+  if (st) {
+    batch_destroy(b);
+    return st;
+  }
+  b->s = new gj_summary(ctx);
+  b->s->f = b->f;
+  b->f->refs++;
+  b->s->borrowed = true;
+  if ((st = alloc_summary(b->f->plan, b->s->arena, b->s->S))) {
+    batch_destroy(b);
+    return st;
+  }
+  // record factor build + summary of every query as one graph
+  if ((st = check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream")) ||
+      (st = check(hipStreamSynchronize(ctx->stream), "capture")) ||
+      (st = check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture"))) {
+    batch_destroy(b);
+    return st;
+  }
+  launch_factors(b->f->plan, b->f->F, b->cap);
+  launch_summary(b->f->plan, b->f->F, b->s->S, b->cap);
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipStreamEndCapture(b->cap, &b->graph);
+  if ((st = check(e1, "batch kernels")) || (st = check(e2, "end capture")) ||
+      (st = check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate"))) {
+    batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return GJ_OK;
+}
+
+gj_status gj_batch_launch(gj_batch* b, void* hip_stream) {
+  if (!b) {
+    set_error("gj_batch_launch: null batch");
+    return GJ_E_INVALID;
+  }
+  b->counters_valid = false;
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : b->ctx->stream;
+  return check(hipGraphLaunch(b->exec, s), "graph launch");
+}
+
+gj_status gj_batch_launch_eager(gj_batch* b, void* hip_stream) {
+  if (!b) {
+    set_error("gj_batch_launch_eager: null batch");
+    return GJ_E_INVALID;
+  }
+  b->counters_valid = false;
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : b->ctx->stream;
+  launch_factors(b->f->plan, b->f->F, s);
+  launch_summary(b->f->plan, b->f->F, b->s->S, s);
+  return check(hipGetLastError(), "batch kernels");
+}
+
+const int64_t* gj_batch_join_sizes(const gj_batch* b) { return b ? b->s->S.qsize : nullptr; }
+const int32_t* gj_batch_status(const gj_batch* b) { return b ? b->s->S.qstatus : nullptr; }
+
+gj_status gj_batch_summary(gj_batch* b, int32_t q, const gj_summary** out) {
+  if (!b || !out || q < 0 || q >= b->f->plan.nq) {
+    set_error("gj_batch_summary: bad argument");
+    return GJ_E_INVALID;
+  }
+  hipStream_t s = b->ctx->stream;
+  gj_status st;
+  if (!b->counters_valid) {
+    b->cnt_host.assign((size_t)b->f->plan.nt * CNT_STRIDE, 0);
+    if ((st = check(hipMemcpyAsync(b->cnt_host.data(), b->f->F.cnt, b->cnt_host.size() * 8, hipMemcpyDeviceToHost,
+                                   s),
+                    "counters")) ||
+        (st = check(hipStreamSynchronize(s), "counters")))
+      return st;
+    b->counters_valid = true;
+  }
+  int64_t js = 0;
+  int32_t qs = 0;
+  if ((st = check(hipMemcpyAsync(&js, b->s->S.qsize + q, 8, hipMemcpyDeviceToHost, s), "join size")) ||
+      (st = check(hipMemcpyAsync(&qs, b->s->S.qstatus + q, 4, hipMemcpyDeviceToHost, s), "status")) ||
+      (st = check(hipStreamSynchronize(s), "join size")))
+    return st;
+  if (qs == GJ_E_OVERFLOW) {
+    set_error("query %d: join size does not fit below 2^63-1", q);
+    return GJ_E_OVERFLOW;
+  }
+  gj_summary* v = new gj_summary(b->ctx);
+  v->f = b->f;
+  v->S = b->s->S;
+  v->query = q;
+  v->borrowed = true;
+  v->cnt_host = b->cnt_host;
+  v->join_size = js;
+  b->views.push_back(v);
+  *out = v;
+  return GJ_OK;
+}
+
+void gj_free_batch(gj_batch* b) { batch_destroy(b); }
+
+}  // extern "C"

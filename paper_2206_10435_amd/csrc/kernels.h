@@ -1,0 +1,33 @@
+// Host-side launchers of the device kernels (one namespace, defined in the
+// .hip translation units).  All launches are asynchronous on stream `s`.
+#pragma once
+#include "gj_internal.h"
+
+namespace gjk {
+
+// factor.hip
+void fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v0, int32_t v1);
+void minmax(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, int32_t* mm);
+void pack(hipStream_t s, int wide, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& P);
+void radix_pass(hipStream_t s, int wide, int items, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab,
+                const TDesc* D, const FPtrs& P, int pass);
+void runs(hipStream_t s, int wide, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,
+          const FPtrs& P);
+void runs_scan(hipStream_t s, const int32_t* tabs, int ntab, const TDesc* D, const FPtrs& P);
+void runs_write(hipStream_t s, int wide, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& P);
+void tile_scan_pair(hipStream_t s, const int32_t* tabs, int ntab, const TDesc* D, uint64_t* agg, int64_t* cnt, int ca,
+                    int cb);
+
+// summary.hip
+void fill_i64(hipStream_t s, int64_t* p, int64_t n, int64_t v);
+void up_pass(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,
+             const FPtrs& F, const SPtrs& S);
+void down_pass(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F, const SPtrs& S);
+void compact(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,
+             const FPtrs& F, const SPtrs& S);
+
+// desum.hip
+struct DesumArgs;
+int desummarize(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables, int tuples_per_lane);
+
+}  // namespace gjk

@@ -1,0 +1,119 @@
+// Host-side plan of a set of tables (one query or a batch of queries) and the
+// device buffers of its factors / summaries.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "gj_internal.h"
+
+struct gj_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  gj_alloc_fn alloc = nullptr;
+  gj_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  gj_tune tune{};
+};
+
+namespace gjh {
+
+void set_error(const char* fmt, ...);
+
+// A device allocation made through the context's allocator.
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+class Arena {
+ public:
+  explicit Arena(gj_ctx* c) : ctx(c) {}
+  ~Arena() { release(); }
+  // returns nullptr on failure (error already set)
+  void* get(size_t bytes);
+  template <typename T>
+  T* get_n(int64_t n) {
+    return reinterpret_cast<T*>(get((size_t)std::max<int64_t>(n, 1) * sizeof(T)));
+  }
+  void release();
+  gj_ctx* ctx;
+  std::vector<Buf> bufs;
+};
+
+struct HTable {
+  int64_t n = 0;
+  int k = 0;
+  const int32_t* cols[MAXK] = {};
+  int parent = -1;  // global index
+  int sep = 0, pcol = 0;
+  int query = 0, local = 0;
+  std::vector<int> children;  // global indices, ascending
+  int depth = 0, height = 0;
+};
+
+struct WL {
+  int off = 0, n = 0;  // range in the work-item array
+  int toff = 0, tn = 0;  // range in the table-id array
+};
+
+struct Plan {
+  gj_ctx* ctx = nullptr;
+  int nq = 0, nt = 0;
+  std::vector<int> qfirst;  // nq + 1
+  std::vector<HTable> ht;
+  std::vector<TDesc> td;
+  int64_t S = 0, key_slots = 0, link_slots = 0, agg_slots = 0, hist_slots = 0, word_units = 0;
+  int max_height = 0, max_depth = 0, max_passes = 0;
+  // work lists
+  std::vector<WorkItem> wl_host;
+  std::vector<int32_t> tabs_host;
+  WL all;                    // GJ_TILE tiles of every table
+  WL allw[2];                // the same, split by sort-word width
+  std::vector<WL> sort[2];   // [wide][pass]
+  std::vector<WL> up;        // [height]
+  std::vector<WL> down;      // [depth]: parents at depth-1 that have children
+  WorkItem* d_wl = nullptr;
+  int32_t* d_tabs = nullptr;
+  TDesc* d_desc = nullptr;
+  int sort_items[2] = {16, 8};
+  int radix_bits = 8;
+
+  WL add_list(const std::vector<int>& tables, int tile, bool sort_tiles);
+};
+
+// Validates `nq` graphs; fills the host tables of the plan (no device work).
+gj_status plan_tables(Plan& P, int nq, const int* q_off, const gj_table* tables, const gj_join_graph* graphs);
+// Assigns slots, reads the key ranges on the device (one synchronization),
+// picks the sort-word layout, builds the work lists and uploads everything.
+gj_status plan_device(Plan& P, Arena& A, FPtrs& F);
+// Factor build kernels (asynchronous, capturable).
+void launch_factors(const Plan& P, const FPtrs& F, hipStream_t s);
+// Summary kernels (asynchronous, capturable).
+void launch_summary(const Plan& P, const FPtrs& F, const SPtrs& S, hipStream_t s);
+gj_status alloc_summary(const Plan& P, Arena& A, SPtrs& S);
+
+gj_status check(hipError_t e, const char* what);
+
+}  // namespace gjh
+
+struct gj_factors {
+  gj_ctx* ctx = nullptr;
+  gjh::Plan plan;
+  gjh::Arena arena;
+  FPtrs F{};
+  std::vector<int64_t> cnt_host;  // host copy of the counters
+  int refs = 1;
+  explicit gj_factors(gj_ctx* c) : ctx(c), arena(c) {}
+};
+
+struct gj_summary {
+  gj_ctx* ctx = nullptr;
+  gj_factors* f = nullptr;
+  gjh::Arena arena;
+  SPtrs S{};
+  int query = 0;        // which query of the plan this summary describes
+  bool borrowed = false;  // part of a batch: not freed by gj_free_summary
+  std::vector<int64_t> cnt_host;
+  int64_t join_size = 0;
+  explicit gj_summary(gj_ctx* c) : ctx(c), arena(c) {}
+};

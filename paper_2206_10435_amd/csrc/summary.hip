@@ -1,0 +1,366 @@
+// Stage 2 -- summary.  Integer sum-product message passing over the join tree.
+//
+// Upward (Sec. 3.3, Algorithm 2; variable elimination Eq. 4 from the leaves):
+// for every entry e of table t, U_t(e) = product over t's children ch of the
+// child's message at e's value of the joining column (1 at a leaf); the
+// message of t is M_t(s) = sum of c_t(e) * U_t(e) over t's entries with
+// separator value s, and the root's sum is the join size (Eq. 3's Z).
+//   k_up_agg    U per entry (looking each child value up in the child's
+//               sorted separator values, which also records the entry ->
+//               child-group link), tile aggregates of a segmented scan of c*U
+//   k_seg_tiles carry-in of every tile
+//   k_up_scan   exclusive prefix of c*U inside each separator group (the block
+//               offsets used by desummarization) and the group totals M
+// Downward (Sec. 3.5, Algorithms 3-4 condition each level on the levels
+// above): D_t(s) = sum over parent entries e' with value s in the joining
+// column of c_p(e') * D_p(e') * product of the other children's messages;
+// scattered with 64-bit atomics (exact: every partial sum is bounded by the
+// join size once the upward pass has not overflowed).
+// Compaction keeps entries with F = c*U*D > 0 and groups with M*D > 0 (Sec.
+// 3.3: entries of frequency below 1 are excluded) and re-links them.
+#include "gj_internal.h"
+#include "kernels.h"
+
+namespace {
+
+// index of v in the ascending array a[0..n), or -1
+__device__ __forceinline__ int32_t find_sorted(const int32_t* __restrict__ a, int64_t n, int32_t v) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < n && a[lo] == v) ? (int32_t)lo : -1;
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void __launch_bounds__(GJ_BLOCK) k_up_agg(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
+                                                     FPtrs F, SPtrs S) {
+  __shared__ uint64_t shv[GJ_WAVES];
+  __shared__ uint32_t shf[GJ_WAVES];
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  uint64_t av = 0;
+  uint32_t af = 0;
+  if (base < M) {
+    for (int r = 0; r < GJ_ROUNDS; ++r) {
+      const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+      uint64_t cu = 0;
+      uint32_t head = 0;
+      if (e < M) {
+        const int64_t se = d.off + e;
+        uint64_t U = 1;
+#pragma unroll
+        for (int i = 0; i < MAXC; ++i) {
+          if (i < d.nchild) {
+            const int ch = d.child[i];
+            const TDesc& dc = D[ch];
+            const int32_t v = F.ekey[d.key_off + (int64_t)d.child_col[i] * d.n + e];
+            const int32_t j = find_sorted(F.gval + dc.off, F.cnt[ch * CNT_STRIDE + CNT_G], v);
+            S.link[dc.link_off + e] = j;
+            const uint64_t m = j >= 0 ? (uint64_t)S.Mg[dc.off + j] : 0ULL;
+            U = smul(U, m);
+          }
+        }
+        const uint64_t c = (uint64_t)(F.eend[se] - F.estart[se]);
+        cu = smul(c, U);
+        S.U[se] = (int64_t)U;
+        head = (e == 0 || F.egrp[se] != F.egrp[se - 1]) ? 1u : 0u;
+      }
+      uint64_t tv;
+      uint32_t tf;
+      block_seg_incl(cu, head, shv, shf, tv, tf);
+      av = tf ? tv : sadd(av, tv);
+      af |= tf;
+    }
+  }
+  if (threadIdx.x == 0) {
+    F.agg[d.agg_off + w.tile] = av;
+    F.agg2[d.agg_off + w.tile] = af;
+  }
+}
+
+// One block per table: carry-in value of every tile of the segmented scan
+// (exclusive), written over the tile aggregate.
+__global__ void __launch_bounds__(GJ_BLOCK) k_seg_tiles(const int32_t* __restrict__ tabs, const TDesc* __restrict__ D,
+                                                        FPtrs F) {
+  __shared__ uint64_t shv[GJ_WAVES];
+  __shared__ uint32_t shf[GJ_WAVES];
+  __shared__ uint64_t incl[GJ_BLOCK];
+  const int t = tabs[blockIdx.x];
+  const TDesc& d = D[t];
+  uint64_t cv = 0;
+  for (int64_t i0 = 0; i0 < d.ntiles; i0 += GJ_BLOCK) {
+    const int64_t i = i0 + threadIdx.x;
+    uint64_t v = 0;
+    uint32_t f = 0;
+    if (i < d.ntiles) {
+      v = F.agg[d.agg_off + i];
+      f = (uint32_t)F.agg2[d.agg_off + i];
+    }
+    uint64_t tv;
+    uint32_t tf;
+    block_seg_incl(v, f, shv, shf, tv, tf);
+    const uint64_t mine = f ? v : sadd(cv, v);  // inclusive, with the carry
+    incl[threadIdx.x] = mine;
+    __syncthreads();
+    const uint64_t ex = threadIdx.x == 0 ? cv : incl[threadIdx.x - 1];
+    if (i < d.ntiles) F.agg[d.agg_off + i] = ex;
+    cv = incl[GJ_BLOCK - 1];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(GJ_BLOCK) k_up_scan(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
+                                                      FPtrs F, SPtrs S) {
+  __shared__ uint64_t shv[GJ_WAVES];
+  __shared__ uint32_t shf[GJ_WAVES];
+  __shared__ uint64_t incl[GJ_BLOCK];
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  if (base >= M) return;
+  uint64_t cv = F.agg[d.agg_off + w.tile];
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+    const int64_t se = d.off + e;
+    uint64_t cu = 0;
+    uint32_t head = 0;
+    const bool valid = e < M;
+    if (valid) {
+      const uint64_t c = (uint64_t)(F.eend[se] - F.estart[se]);
+      cu = smul(c, (uint64_t)S.U[se]);
+      head = (e == 0 || F.egrp[se] != F.egrp[se - 1]) ? 1u : 0u;
+    }
+    uint64_t v = cu;
+    uint32_t f = head;
+    uint64_t tv;
+    uint32_t tf;
+    block_seg_incl(v, f, shv, shf, tv, tf);
+    const uint64_t mine = f ? v : sadd(cv, v);
+    incl[threadIdx.x] = mine;
+    __syncthreads();
+    if (valid) {
+      const uint64_t ex = head ? 0ULL : (threadIdx.x == 0 ? cv : incl[threadIdx.x - 1]);
+      S.pre[se] = (int64_t)ex;
+      const bool last = (e + 1 == M) || F.egrp[se + 1] != F.egrp[se];
+      if (last) {
+        S.Mg[d.off + F.egrp[se]] = (int64_t)mine;
+        if (d.is_root) {
+          S.qsize[d.query] = (int64_t)mine;
+          S.qstatus[d.query] = mine >= SATV ? GJ_E_OVERFLOW : GJ_OK;
+        }
+      }
+    }
+    cv = incl[GJ_BLOCK - 1];
+    __syncthreads();
+  }
+}
+
+// Downward messages into the children of the tables in the work list.
+__global__ void __launch_bounds__(GJ_BLOCK) k_down(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
+                                                   FPtrs F, SPtrs S) {
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  if (base >= M) return;
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+    if (e >= M) break;
+    const int64_t se = d.off + e;
+    const uint64_t U = (uint64_t)S.U[se];
+    if (U == 0) continue;
+    const uint64_t Dp = d.is_root ? 1ULL : (uint64_t)S.Dg[d.off + F.egrp[se]];
+    if (Dp == 0) continue;
+    const uint64_t c = (uint64_t)(F.eend[se] - F.estart[se]);
+    const uint64_t b = smul(c, Dp);
+    uint64_t m[MAXC];
+    int32_t j[MAXC];
+#pragma unroll
+    for (int i = 0; i < MAXC; ++i) {
+      m[i] = 1;
+      j[i] = 0;
+      if (i < d.nchild) {
+        const TDesc& dc = D[d.child[i]];
+        j[i] = S.link[dc.link_off + e];
+        m[i] = (uint64_t)S.Mg[dc.off + j[i]];
+      }
+    }
+    // product of all the other children's messages: prefix * suffix
+    uint64_t pre[MAXC];
+    uint64_t acc = 1;
+#pragma unroll
+    for (int i = 0; i < MAXC; ++i) {
+      pre[i] = acc;
+      acc = smul(acc, m[i]);
+    }
+    acc = 1;
+#pragma unroll
+    for (int i = MAXC - 1; i >= 0; --i) {
+      if (i < d.nchild) {
+        const TDesc& dc = D[d.child[i]];
+        const uint64_t term = smul(b, smul(pre[i], acc));
+        atomicAdd((unsigned long long*)(S.Dg + dc.off + j[i]), (unsigned long long)term);
+      }
+      acc = smul(acc, m[i]);
+    }
+  }
+}
+
+// Survivors per tile: entries with U > 0 and D > 0, groups with M > 0 and D > 0.
+__device__ __forceinline__ bool entry_survives(const TDesc& d, const FPtrs& F, const SPtrs& S, int64_t se) {
+  if (S.U[se] == 0) return false;
+  return d.is_root || S.Dg[d.off + F.egrp[se]] > 0;
+}
+__device__ __forceinline__ bool group_survives(const TDesc& d, const SPtrs& S, int64_t sg) {
+  return S.Mg[sg] > 0 && (d.is_root || S.Dg[sg] > 0);
+}
+
+__global__ void __launch_bounds__(GJ_BLOCK) k_compact_count(const WorkItem* __restrict__ wl,
+                                                            const TDesc* __restrict__ D, FPtrs F, SPtrs S) {
+  __shared__ uint64_t sh[GJ_WAVES];
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t G = F.cnt[w.t * CNT_STRIDE + CNT_G];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  uint64_t acc = 0;
+  if (base < M) {
+    for (int r = 0; r < GJ_ROUNDS; ++r) {
+      const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+      if (e < M && entry_survives(d, F, S, d.off + e)) acc += 1;
+      if (e < G && group_survives(d, S, d.off + e)) acc += 1ULL << 32;
+    }
+  }
+  uint64_t tot;
+  block_excl_sum(acc, sh, tot);
+  if (threadIdx.x == 0) F.agg[d.agg_off + w.tile] = tot;
+}
+
+__global__ void __launch_bounds__(GJ_BLOCK) k_compact_write(const WorkItem* __restrict__ wl,
+                                                            const TDesc* __restrict__ D, FPtrs F, SPtrs S) {
+  __shared__ uint64_t sh[GJ_WAVES];
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t G = F.cnt[w.t * CNT_STRIDE + CNT_G];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  if (base >= M) return;
+  uint64_t carry = F.agg[d.agg_off + w.tile];
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+    const int64_t se = d.off + e;
+    const bool ve = e < M, vg = e < G;
+    const bool es = ve && entry_survives(d, F, S, se);
+    const bool gs = vg && group_survives(d, S, se);
+    uint64_t tot;
+    const uint64_t ex = block_excl_sum((uint64_t)es | ((uint64_t)gs << 32), sh, tot) + carry;
+    carry += tot;
+    const int64_t ci = (int64_t)(uint32_t)ex;
+    const int64_t gi = (int64_t)(ex >> 32);
+    if (ve) {
+      S.e2c[se] = (int32_t)ci;
+      if (es) {
+        const int64_t sc = d.off + ci;
+        const uint64_t c = (uint64_t)(F.eend[se] - F.estart[se]);
+        const uint64_t U = (uint64_t)S.U[se];
+        const uint64_t Dv = d.is_root ? 1ULL : (uint64_t)S.Dg[d.off + F.egrp[se]];
+        for (int k = 0; k < d.k; ++k)
+          S.ckey[d.key_off + (int64_t)k * d.n + ci] = F.ekey[d.key_off + (int64_t)k * d.n + e];
+        S.cc[sc] = (int64_t)c;
+        S.cU[sc] = (int64_t)U;
+        S.cD[sc] = (int64_t)Dv;
+        S.cF[sc] = (int64_t)smul(smul(c, U), Dv);
+        S.cpre[sc] = S.pre[se];
+        S.cstart[sc] = F.estart[se];
+      }
+    }
+    if (vg) {
+      S.g2c[se] = gs ? (int32_t)gi : -1;
+      if (gs) {
+        const int64_t sg = d.off + gi;
+        S.cgval[sg] = F.gval[se];
+        S.cgM[sg] = S.Mg[se];
+        S.cgD[sg] = d.is_root ? 1 : S.Dg[se];
+      }
+    }
+  }
+}
+
+// Second compaction pass (needs every e2c / g2c): compacted group ranges and
+// the compacted parent-entry -> child-group links.
+__global__ void __launch_bounds__(GJ_BLOCK) k_compact_links(const WorkItem* __restrict__ wl,
+                                                            const TDesc* __restrict__ D, FPtrs F, SPtrs S) {
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t G = F.cnt[w.t * CNT_STRIDE + CNT_G];
+  const int64_t Mc = F.cnt[w.t * CNT_STRIDE + CNT_MC];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  if (base >= M) return;
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+    if (e >= M) break;
+    const int64_t se = d.off + e;
+    if (entry_survives(d, F, S, se)) {
+      const int32_t ci = S.e2c[se];
+      for (int i = 0; i < d.nchild; ++i) {
+        const TDesc& dc = D[d.child[i]];
+        const int32_t j = S.link[dc.link_off + e];
+        S.clink[dc.link_off + ci] = S.g2c[dc.off + j];
+      }
+    }
+    if (e < G) {
+      const int32_t gi = S.g2c[se];
+      if (gi >= 0) {
+        const int32_t lo = F.glo[se], hi = F.ghi[se];
+        S.cglo[d.off + gi] = lo < M ? S.e2c[d.off + lo] : (int32_t)Mc;
+        S.cghi[d.off + gi] = hi < M ? S.e2c[d.off + hi] : (int32_t)Mc;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+namespace gjk {
+
+void fill_i64(hipStream_t s, int64_t* p, int64_t n, int64_t v) {
+  if (n <= 0) return;
+  int blocks = (int)std::min<int64_t>((n + GJ_BLOCK - 1) / GJ_BLOCK, 4096);
+  hipLaunchKernelGGL(k_fill_i64, dim3(blocks), dim3(GJ_BLOCK), 0, s, p, n, v);
+}
+
+void up_pass(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,
+             const FPtrs& F, const SPtrs& S) {
+  if (nwl <= 0) return;
+  hipLaunchKernelGGL(k_up_agg, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
+  hipLaunchKernelGGL(k_seg_tiles, dim3(ntab), dim3(GJ_BLOCK), 0, s, tabs, D, F);
+  hipLaunchKernelGGL(k_up_scan, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
+}
+
+void down_pass(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F, const SPtrs& S) {
+  if (nwl > 0) hipLaunchKernelGGL(k_down, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
+}
+
+void compact(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,
+             const FPtrs& F, const SPtrs& S) {
+  if (nwl <= 0) return;
+  hipLaunchKernelGGL(k_compact_count, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
+  tile_scan_pair(s, tabs, ntab, D, F.agg, F.cnt, CNT_MC, CNT_GC);
+  hipLaunchKernelGGL(k_compact_write, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
+  hipLaunchKernelGGL(k_compact_links, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
+}
+
+}  // namespace gjk

@@ -1,0 +1,399 @@
+"""Thin ctypes binding over ``libgj.so`` (the C ABI declared in include/gj.h).
+
+Argument marshalling only: every step of the join runs in the library's HIP
+kernels.  PyTorch provides device memory (its caching allocator is handed to
+the library as the allocator callback) and the stream.  If the library is
+missing this module raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgj.so")
+
+GJ_OK, GJ_E_INVALID, GJ_E_GRAPH, GJ_E_OVERFLOW, GJ_E_OOM, GJ_E_DEVICE, GJ_E_RANGE = range(7)
+STATUS_NAMES = {0: "GJ_OK", 1: "GJ_E_INVALID", 2: "GJ_E_GRAPH", 3: "GJ_E_OVERFLOW", 4: "GJ_E_OOM",
+                5: "GJ_E_DEVICE", 6: "GJ_E_RANGE"}
+MAX_TABLES, MAX_KEYS, MAX_CHILDREN = 16, 8, 8
+
+
+class GJError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Table(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("n_keys", C.c_int32), ("keys", C.c_void_p)]
+
+
+class _Graph(C.Structure):
+    _fields_ = [("n_tables", C.c_int32), ("parent", C.c_void_p), ("sep_col", C.c_void_p),
+                ("parent_col", C.c_void_p)]
+
+
+class _FactorView(C.Structure):
+    _fields_ = [("n_entries", C.c_int64), ("n_rows", C.c_int64), ("n_keys", C.c_int32),
+                ("keys", C.c_void_p * MAX_KEYS), ("start", C.c_void_p), ("end", C.c_void_p),
+                ("perm", C.c_void_p)]
+
+
+class _SummaryView(C.Structure):
+    _fields_ = [("n_entries", C.c_int64), ("n_keys", C.c_int32), ("keys", C.c_void_p * MAX_KEYS),
+                ("c", C.c_void_p), ("U", C.c_void_p), ("D", C.c_void_p), ("F", C.c_void_p),
+                ("pre", C.c_void_p)]
+
+
+class _EdgeView(C.Structure):
+    _fields_ = [("n", C.c_int64), ("s", C.c_void_p), ("M", C.c_void_p), ("D", C.c_void_p)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("sort_items", C.c_int32), ("radix_bits", C.c_int32), ("desum_rounds", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_lib = None
+
+# every exported function: name -> (restype, argtypes)
+_vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+SIGNATURES = {
+    "gj_ctx_create": (C.c_int, [C.c_int, _vp, ALLOC_FN, FREE_FN, _vp, _vp]),
+    "gj_ctx_destroy": (None, [_vp]),
+    "gj_last_error": (C.c_char_p, []),
+    "gj_validate": (C.c_int, [_vp, _vp]),
+    "gj_build_factors": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "gj_factor_table": (C.c_int, [_vp, _i32, _vp]),
+    "gj_free_factors": (None, [_vp]),
+    "gj_summarize": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "gj_summary_table": (C.c_int, [_vp, _i32, _vp]),
+    "gj_summary_edge": (C.c_int, [_vp, _i32, _vp]),
+    "gj_summary_join_size": (_i64, [_vp]),
+    "gj_free_summary": (None, [_vp]),
+    "gj_desummarize": (C.c_int, [_vp, _vp, _i64, _i64, _i32, _vp, _vp]),
+    "gj_result_columns": (_i32, [_vp]),
+    "gj_unroll_gfjs": (C.c_int, [_vp, _vp, _i64, _i64, _vp, _vp, _vp]),
+    "gj_weighted_forward": (C.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
+    "gj_weighted_backward": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "gj_free_wstate": (None, [_vp]),
+    "gj_batch_create": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "gj_batch_launch": (C.c_int, [_vp, _vp]),
+    "gj_batch_launch_eager": (C.c_int, [_vp, _vp]),
+    "gj_batch_join_sizes": (_vp, [_vp]),
+    "gj_batch_status": (_vp, [_vp]),
+    "gj_batch_summary": (C.c_int, [_vp, _i32, _vp]),
+    "gj_free_batch": (None, [_vp]),
+    "gj_download": (C.c_int, [_vp, _vp, _vp, _sz]),
+    "gj_ctx_set_tune": (C.c_int, [_vp, _vp]),
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgj.so (raises if it has not been built: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing; build it with `python -m paper_2206_10435_amd.build`")
+    L = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != GJ_OK:
+        raise GJError(rc, load_library().gj_last_error().decode())
+
+
+def _graph_struct(parent, sep_col, parent_col):
+    n = len(parent)
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.int32)) for a in (parent, sep_col, parent_col)]
+    return _Graph(n, *[a.ctypes.data for a in arrs]), arrs
+
+
+def validate(n_rows: Sequence[int], n_keys: Sequence[int], parent, sep_col, parent_col) -> None:
+    """Host-only graph validation (no device work); raises GJError."""
+    L = load_library()
+    keep = []
+    tabs = (_Table * len(n_rows))()
+    for t, (n, k) in enumerate(zip(n_rows, n_keys)):
+        fake = (C.c_void_p * max(k, 1))(*([1] * max(k, 1)))  # non-null column placeholders
+        keep.append(fake)
+        tabs[t] = _Table(int(n), int(k), C.cast(fake, C.c_void_p))
+    g, arrs = _graph_struct(parent, sep_col, parent_col)
+    _check(L.gj_validate(tabs, C.byref(g)))
+
+
+class Context:
+    """A device, a stream and PyTorch's caching allocator."""
+
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True):
+        import torch
+
+        self.torch = torch
+        self.L = load_library()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        sptr = self.stream.cuda_stream
+        self._live = {}
+        if torch_allocator:
+            def _alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device, self.stream)
+                except Exception:
+                    return None
+
+            def _free(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc_cb = ALLOC_FN(_alloc)
+            self._free_cb = FREE_FN(_free)
+        else:
+            self._alloc_cb = ALLOC_FN()
+            self._free_cb = FREE_FN()
+        h = C.c_void_p()
+        _check(self.L.gj_ctx_create(device, C.c_void_p(sptr), self._alloc_cb, self._free_cb, None, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.gj_ctx_destroy(self.h)
+            self.h = None
+
+    def set_tune(self, sort_items=16, radix_bits=8, desum_rounds=8):
+        t = Tune(sort_items, radix_bits, desum_rounds, 0)
+        _check(self.L.gj_ctx_set_tune(self.h, C.byref(t)))
+
+    def download(self, ptr: int, n: int, dtype) -> np.ndarray:
+        out = np.empty(max(n, 0), dtype=dtype)
+        if n > 0:
+            _check(self.L.gj_download(self.h, out.ctypes.data_as(C.c_void_p), C.c_void_p(ptr), out.nbytes))
+        return out
+
+    # -- stage 1 ------------------------------------------------------------
+    def build_factors(self, tables: List[List["torch.Tensor"]], parent, sep_col, parent_col) -> "Factors":
+        tabs, keep = _tables_struct(tables)
+        g, arrs = _graph_struct(parent, sep_col, parent_col)
+        h = C.c_void_p()
+        _check(self.L.gj_build_factors(self.h, tabs, C.byref(g), C.byref(h)))
+        return Factors(self, h, len(tables))
+
+    # -- stage 2 ------------------------------------------------------------
+    def summarize(self, f: "Factors") -> "Summary":
+        h = C.c_void_p()
+        q = C.c_int64()
+        _check(self.L.gj_summarize(self.h, f.h, C.byref(h), C.byref(q)))
+        return Summary(self, h, f.n_tables, int(q.value))
+
+    # -- stage 3 ------------------------------------------------------------
+    def desummarize(self, s: "Summary", first_row: int, n_rows: int, out) -> int:
+        """Writes rows [first_row, first_row + n_rows) into `out` (int32 or int64
+        device tensor of at least n_rows * n_tables elements); returns the count."""
+        import torch
+
+        if out.dtype not in (torch.int32, torch.int64) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32/int64 device tensor")
+        if out.numel() < n_rows * s.n_tables:
+            raise ValueError("out is too small")
+        nw = C.c_int64()
+        _check(self.L.gj_desummarize(self.h, s.h, int(first_row), int(n_rows), out.element_size(),
+                                     C.c_void_p(out.data_ptr()), C.byref(nw)))
+        return int(nw.value)
+
+    def unroll_gfjs(self, s: "Summary", first_row: int, n_rows: int):
+        """Paper-literal GFJS of a row range: list of (values, freqs) numpy pairs per result column."""
+        import torch
+
+        L = int(self.L.gj_result_columns(s.h))
+        vals = [torch.empty(max(n_rows, 1), dtype=torch.int32, device=f"cuda:{self.device}") for _ in range(L)]
+        frqs = [torch.empty(max(n_rows, 1), dtype=torch.int64, device=f"cuda:{self.device}") for _ in range(L)]
+        vp = (C.c_void_p * L)(*[v.data_ptr() for v in vals])
+        fp = (C.c_void_p * L)(*[f.data_ptr() for f in frqs])
+        nr = (C.c_int64 * L)()
+        _check(self.L.gj_unroll_gfjs(self.h, s.h, int(first_row), int(n_rows), vp, fp, nr))
+        return [(vals[i][: nr[i]].cpu().numpy(), frqs[i][: nr[i]].cpu().numpy()) for i in range(L)]
+
+    # -- weighted ------------------------------------------------------------
+    def weighted_forward(self, f: "Factors", weights: List["torch.Tensor"]):
+        import torch
+
+        dt = weights[0].dtype
+        if dt not in (torch.float32, torch.float64) or any(w.dtype != dt for w in weights):
+            raise ValueError("weights must all be float32 or all float64")
+        wp = (C.c_void_p * len(weights))(*[w.data_ptr() for w in weights])
+        W = torch.empty((), dtype=torch.float64, device=f"cuda:{self.device}")
+        st = C.c_void_p()
+        _check(self.L.gj_weighted_forward(self.h, f.h, wp, 1 if dt == torch.float64 else 0,
+                                          C.c_void_p(W.data_ptr()), C.byref(st)))
+        return W, WState(self, st)
+
+    def weighted_backward(self, st: "WState", gradW, grads: List["torch.Tensor"]):
+        gp = (C.c_void_p * len(grads))(*[g.data_ptr() for g in grads])
+        _check(self.L.gj_weighted_backward(self.h, st.h, C.c_void_p(gradW.data_ptr()), gp))
+
+    # -- batch ---------------------------------------------------------------
+    def batch_create(self, queries: List[dict], tune: Optional[Tune] = None) -> "Batch":
+        """queries: dicts with 'tables' (list of lists of int32 device tensors), 'parent',
+        'sep_col', 'parent_col'."""
+        tabs_all, keep = [], []
+        qoff = [0]
+        graphs = (_Graph * len(queries))()
+        for qi, q in enumerate(queries):
+            tabs_all.extend(q["tables"])
+            qoff.append(qoff[-1] + len(q["tables"]))
+            g, arrs = _graph_struct(q["parent"], q["sep_col"], q["parent_col"])
+            keep.append(arrs)
+            graphs[qi] = g
+        tabs, keep2 = _tables_struct(tabs_all)
+        qo = np.array(qoff, dtype=np.int32)
+        h = C.c_void_p()
+        _check(self.L.gj_batch_create(self.h, len(queries), qo.ctypes.data_as(C.c_void_p), tabs, graphs,
+                                      C.byref(tune) if tune is not None else None, C.byref(h)))
+        return Batch(self, h, [len(q["tables"]) for q in queries], keep=(keep, keep2, queries))
+
+
+def _tables_struct(tables):
+    tabs = (_Table * len(tables))()
+    keep = []
+    for t, cols in enumerate(tables):
+        for c in cols:
+            if c.dtype.__str__() != "torch.int32" or not c.is_contiguous() or not c.is_cuda:
+                raise ValueError("key columns must be contiguous int32 device tensors")
+        ptrs = (C.c_void_p * max(len(cols), 1))(*[c.data_ptr() for c in cols])
+        keep.append(ptrs)
+        n = int(cols[0].numel()) if cols else 0
+        tabs[t] = _Table(n, len(cols), C.cast(ptrs, C.c_void_p))
+    return tabs, keep
+
+
+class Factors:
+    def __init__(self, ctx: Context, h, n_tables: int):
+        self.ctx, self.h, self.n_tables = ctx, h, n_tables
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.ctx.h:
+            self.ctx.L.gj_free_factors(self.h)
+            self.h = None
+
+    def table(self, t: int) -> dict:
+        v = _FactorView()
+        _check(self.ctx.L.gj_factor_table(self.h, t, C.byref(v)))
+        M, N, k = int(v.n_entries), int(v.n_rows), int(v.n_keys)
+        d = self.ctx.download
+        keys = np.stack([d(v.keys[c], M, np.int32) for c in range(k)], axis=1) if k else np.zeros((M, 0), np.int32)
+        start = d(v.start, M, np.int32)
+        end = d(v.end, M, np.int32)
+        return dict(keys=keys, start=start, end=end, count=(end - start).astype(np.int64),
+                    perm=d(v.perm, N, np.int32))
+
+
+class Summary:
+    def __init__(self, ctx: Context, h, n_tables: int, join_size: int, borrowed: bool = False):
+        self.ctx, self.h, self.n_tables, self.join_size, self.borrowed = ctx, h, n_tables, join_size, borrowed
+
+    def __del__(self):
+        if not self.borrowed and getattr(self, "h", None) is not None and self.ctx.h:
+            self.ctx.L.gj_free_summary(self.h)
+            self.h = None
+
+    def table(self, t: int) -> dict:
+        v = _SummaryView()
+        _check(self.ctx.L.gj_summary_table(self.h, t, C.byref(v)))
+        M, k = int(v.n_entries), int(v.n_keys)
+        d = self.ctx.download
+        keys = np.stack([d(v.keys[c], M, np.int32) for c in range(k)], axis=1)
+        return dict(keys=keys, c=d(v.c, M, np.int64), U=d(v.U, M, np.int64), D=d(v.D, M, np.int64),
+                    F=d(v.F, M, np.int64), pre=d(v.pre, M, np.int64))
+
+    def edge(self, t: int) -> dict:
+        v = _EdgeView()
+        _check(self.ctx.L.gj_summary_edge(self.h, t, C.byref(v)))
+        n = int(v.n)
+        d = self.ctx.download
+        return dict(s=d(v.s, n, np.int32), M=d(v.M, n, np.int64), D=d(v.D, n, np.int64))
+
+
+class WState:
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.ctx.h:
+            self.ctx.L.gj_free_wstate(self.h)
+            self.h = None
+
+
+class Batch:
+    def __init__(self, ctx: Context, h, n_tables: List[int], keep=None):
+        self.ctx, self.h, self.n_tables, self._keep = ctx, h, n_tables, keep
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.ctx.h:
+            self.ctx.L.gj_free_batch(self.h)
+            self.h = None
+
+    def launch(self, graph: bool = True, stream=None):
+        sp = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        fn = self.ctx.L.gj_batch_launch if graph else self.ctx.L.gj_batch_launch_eager
+        _check(fn(self.h, sp))
+
+    def results(self):
+        nq = len(self.n_tables)
+        js = self.ctx.download(self.ctx.L.gj_batch_join_sizes(self.h), nq, np.int64)
+        st = self.ctx.download(self.ctx.L.gj_batch_status(self.h), nq, np.int32)
+        return js, st
+
+    def summary(self, q: int) -> Summary:
+        h = C.c_void_p()
+        _check(self.ctx.L.gj_batch_summary(self.h, q, C.byref(h)))
+        js = int(self.ctx.L.gj_summary_join_size(h))
+        return Summary(self.ctx, h, self.n_tables[q], js, borrowed=True)
+
+
+class WeightedJoinSize:
+    """torch.autograd.Function: W = sum over result tuples of the product of row
+    weights; backward runs the library's adjoint (downward) kernel."""
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, ctx: Context, factors: Factors, *weights):
+        if cls._fn is None:
+            import torch
+
+            class _F(torch.autograd.Function):
+                @staticmethod
+                def forward(fctx, gctx, fac, *ws):
+                    W, st = gctx.weighted_forward(fac, list(ws))
+                    fctx.gctx, fctx.st = gctx, st
+                    fctx.shapes = [(w.shape, w.dtype) for w in ws]
+                    return W
+
+                @staticmethod
+                def backward(fctx, gW):
+                    grads = [torch.empty(s, dtype=dt, device=gW.device) for s, dt in fctx.shapes]
+                    gW64 = gW.detach().to(torch.float64).contiguous()
+                    fctx.gctx.weighted_backward(fctx.st, gW64, grads)
+                    return (None, None, *grads)
+
+            cls._fn = _F
+        return cls._fn.apply(ctx, factors, *weights)
+
+
+def to_device_tables(q, device: int = 0):
+    """Upload a workloads.Query's key columns as int32 device tensors."""
+    import torch
+
+    return [[torch.from_numpy(np.ascontiguousarray(c)).to(f"cuda:{device}") for c in tb] for tb in q.tables]
