@@ -132,6 +132,8 @@ def main():
     build_s = []
 
     def step(record: bool):
+        if record:
+            torch.cuda.synchronize()  # the previous step's expansions must not count as build time
         t0 = time.perf_counter()
         f = ctx.build_factors(tabs, q.parent, q.sep_col, q.parent_col)
         s = ctx.summarize(f)  # returns the join size to the host (synchronizes)

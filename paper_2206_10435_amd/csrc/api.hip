@@ -424,10 +424,12 @@ gj_status alloc_summary(const Plan& P, Arena& A, SPtrs& S) {
   S.cglo = A.get_n<int32_t>(P.S);
   S.cghi = A.get_n<int32_t>(P.S);
   S.clink = A.get_n<int32_t>(P.link_slots);
+  S.ccs = A.get_n<int2>(P.S);
+  S.clr = A.get_n<int2>(P.link_slots);
   S.qsize = A.get_n<int64_t>(P.nq);
   S.qstatus = A.get_n<int32_t>(P.nq);
   void* all[] = {S.U,  S.pre,    S.Mg,    S.Dg,  S.link, S.e2c,  S.g2c,  S.ckey,  S.cc,    S.cU,   S.cD,
-                 S.cF, S.cpre,   S.cstart, S.cgval, S.cgM, S.cgD,  S.cglo, S.cghi, S.clink, S.qsize, S.qstatus};
+                 S.cF, S.cpre,   S.cstart, S.cgval, S.cgM, S.cgD,  S.cglo, S.cghi, S.clink, S.qsize, S.qstatus, S.ccs, S.clr};
   for (void* p : all)
     if (!p) return GJ_E_OOM;
   return GJ_OK;
@@ -482,7 +484,8 @@ gj_status gj_ctx_create(int device, void* hip_stream, gj_alloc_fn alloc, gj_free
   c->user = user;
   c->tune.sort_items = 16;
   c->tune.radix_bits = 8;
-  c->tune.desum_rounds = 8;
+  c->tune.desum_rounds = 16;
+  c->tune.desum_stage = 4;
   *out = c;
   return GJ_OK;
 }
@@ -494,9 +497,11 @@ gj_status gj_ctx_set_tune(gj_ctx* ctx, const gj_tune* tune) {
     set_error("gj_ctx_set_tune: null argument");
     return GJ_E_INVALID;
   }
+  const int stg = tune->desum_stage;
   if ((tune->sort_items != 8 && tune->sort_items != 16) || tune->radix_bits < 4 || tune->radix_bits > 8 ||
-      tune->desum_rounds < 1 || tune->desum_rounds > 64) {
-    set_error("gj_ctx_set_tune: sort_items in {8,16}, radix_bits in [4,8], desum_rounds in [1,64]");
+      tune->desum_rounds < 1 || tune->desum_rounds > 1024 || !(stg == 2 || stg == 4 || stg == 8)) {
+    set_error("gj_ctx_set_tune: sort_items in {8,16}, radix_bits in [4,8], desum_rounds in [1,1024], "
+              "desum_stage in {2,4,8}");
     return GJ_E_INVALID;
   }
   ctx->tune = *tune;
@@ -701,6 +706,8 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
     T.cglo = s->S.cglo + d.off;
     T.cghi = s->S.cghi + d.off;
     T.cgM = s->S.cgM + d.off;
+    T.ccs = s->S.ccs + d.off;
+    T.clr = d.parent >= 0 ? s->S.clr + d.link_off : nullptr;
     T.parent = d.parent >= 0 ? d.parent - base : -1;
   }
   a.first = first_row;
@@ -708,7 +715,7 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
   a.n_root = s->cnt_host[base * CNT_STRIDE + CNT_MC];
   a.out = out;
   if (nw > 0) {
-    if (gjk::desummarize(ctx->stream, a, rowid_bytes, n, ctx->tune.desum_rounds) != 0) {
+    if (gjk::desummarize(ctx->stream, a, rowid_bytes, n, ctx->tune.desum_rounds, ctx->tune.desum_stage) != 0) {
       set_error("gj_desummarize: chunk too large for one launch");
       return GJ_E_INVALID;
     }

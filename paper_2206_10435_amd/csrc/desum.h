@@ -14,6 +14,8 @@ struct DTab {
   const int32_t* cglo;    // (t >= 1) surviving group -> first surviving entry
   const int32_t* cghi;    // (t >= 1) surviving group -> end of its entries
   const int64_t* cgM;     // (t >= 1) surviving group -> its upward message M
+  const int2* ccs;        // surviving entry -> (row count, first position in perm)
+  const int2* clr;        // (t >= 1) surviving parent entry -> [first, end) of t's entries
   int32_t parent;
 };
 
@@ -28,6 +30,5 @@ struct DesumArgs {
   int32_t tuples_per_lane;
 };
 
-int desum_round(int n_tables, int rowid_bytes);
 
 }  // namespace gjk

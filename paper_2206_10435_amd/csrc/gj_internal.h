@@ -106,6 +106,8 @@ struct SPtrs {
   int32_t* cglo;
   int32_t* cghi;
   int32_t* clink;
+  int2* ccs;  // surviving entry -> (row count, first position in perm)
+  int2* clr;  // surviving parent entry -> (first, end) surviving entry of the child's group
   int64_t* qsize;
   int32_t* qstatus;
 };

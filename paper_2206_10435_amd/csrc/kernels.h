@@ -28,6 +28,7 @@ void compact(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, in
 
 // desum.hip
 struct DesumArgs;
-int desummarize(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables, int tuples_per_lane);
+// returns -1 if the launch does not fit one grid
+int desummarize(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables, int rounds_per_lane, int stage);
 
 }  // namespace gjk

@@ -284,6 +284,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_compact_write(const WorkItem* __re
         S.cF[sc] = (int64_t)smul(smul(c, U), Dv);
         S.cpre[sc] = S.pre[se];
         S.cstart[sc] = F.estart[se];
+        S.ccs[sc] = make_int2((int)c, F.estart[se]);
       }
     }
     if (vg) {
@@ -318,7 +319,14 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_compact_links(const WorkItem* __re
       for (int i = 0; i < d.nchild; ++i) {
         const TDesc& dc = D[d.child[i]];
         const int32_t j = S.link[dc.link_off + e];
-        S.clink[dc.link_off + ci] = S.g2c[dc.off + j];
+        const int32_t gc = S.g2c[dc.off + j];
+        S.clink[dc.link_off + ci] = gc;
+        // the child's group range in its compacted entries
+        const int64_t Mch = F.cnt[d.child[i] * CNT_STRIDE + CNT_M];
+        const int64_t Mcch = F.cnt[d.child[i] * CNT_STRIDE + CNT_MC];
+        const int32_t glo = F.glo[dc.off + j], ghi = F.ghi[dc.off + j];
+        S.clr[dc.link_off + ci] = make_int2(glo < Mch ? S.e2c[dc.off + glo] : (int32_t)Mcch,
+                                            ghi < Mch ? S.e2c[dc.off + ghi] : (int32_t)Mcch);
       }
     }
     if (e < G) {

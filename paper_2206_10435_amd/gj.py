@@ -55,7 +55,7 @@ class _EdgeView(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("sort_items", C.c_int32), ("radix_bits", C.c_int32), ("desum_rounds", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("desum_stage", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -149,14 +149,21 @@ class Context:
         sptr = self.stream.cuda_stream
         self._live = {}
         if torch_allocator:
+            alloc_fn = torch.cuda.caching_allocator_alloc
+            delete_fn = torch.cuda.caching_allocator_delete
+            stream_ = self.stream
+
             def _alloc(nbytes, user):
                 try:
-                    return torch.cuda.caching_allocator_alloc(int(nbytes), device, self.stream)
+                    return alloc_fn(int(nbytes), device, stream_)
                 except Exception:
                     return None
 
             def _free(ptr, user):
-                torch.cuda.caching_allocator_delete(ptr)
+                try:
+                    delete_fn(ptr)
+                except Exception:
+                    pass  # interpreter shutdown: the process is releasing the device anyway
 
             self._alloc_cb = ALLOC_FN(_alloc)
             self._free_cb = FREE_FN(_free)
@@ -172,8 +179,8 @@ class Context:
             self.L.gj_ctx_destroy(self.h)
             self.h = None
 
-    def set_tune(self, sort_items=16, radix_bits=8, desum_rounds=8):
-        t = Tune(sort_items, radix_bits, desum_rounds, 0)
+    def set_tune(self, sort_items=16, radix_bits=8, desum_rounds=16, desum_stage=4):
+        t = Tune(sort_items, radix_bits, desum_rounds, desum_stage)
         _check(self.L.gj_ctx_set_tune(self.h, C.byref(t)))
 
     def download(self, ptr: int, n: int, dtype) -> np.ndarray:

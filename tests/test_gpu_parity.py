@@ -210,11 +210,11 @@ def test_tune_variants_same_result(gctx, oracle_mod):
     o = oracle_mod.Oracle(q)
     _say("case tune", o.join_size())
     try:
-        for si, rb, dr in [(8, 4, 1), (16, 6, 3), (8, 8, 17)]:
-            gctx.set_tune(si, rb, dr)
+        for si, rb, dr, ds in [(8, 4, 1, 4), (16, 6, 3, 2), (8, 8, 17, 8), (16, 7, 5, 2), (16, 8, 1, 8)]:
+            gctx.set_tune(si, rb, dr, ds)
             _full(gctx, q, o)
     finally:
-        gctx.set_tune(16, 8, 8)
+        gctx.set_tune()
 
 
 def test_overflow_reported(gctx, oracle_mod):
