@@ -291,9 +291,11 @@ gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
   P.all = P.add_list(all, GJ_TILE, false);
   // key ranges (one synchronization)
   int32_t* d_mm = A.get_n<int32_t>((int64_t)P.nt * MAXK * 2);
+  int32_t* d_mmt = A.get_n<int32_t>(P.agg_slots * MAXK * 2);
   TDesc* d_desc = A.get_n<TDesc>(P.nt);
   WorkItem* d_wl0 = A.get_n<WorkItem>(std::max(1, P.all.n));
-  if (!d_mm || !d_desc || !d_wl0) return GJ_E_OOM;
+  int32_t* d_tabs0 = A.get_n<int32_t>(std::max(1, P.all.tn));
+  if (!d_mm || !d_mmt || !d_desc || !d_wl0 || !d_tabs0) return GJ_E_OOM;
   gj_status st;
   if ((st = check(hipMemcpyAsync(d_desc, P.td.data(), sizeof(TDesc) * P.nt, hipMemcpyHostToDevice, s), "upload")))
     return st;
@@ -301,8 +303,12 @@ gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
                                  hipMemcpyHostToDevice, s),
                   "upload")))
     return st;
+  if ((st = check(hipMemcpyAsync(d_tabs0, P.tabs_host.data(), sizeof(int32_t) * std::max(1, P.all.tn),
+                                 hipMemcpyHostToDevice, s),
+                  "upload")))
+    return st;
   gjk::fill_i32(s, d_mm, (int64_t)P.nt * MAXK * 2, INT32_MAX, INT32_MIN);
-  gjk::minmax(s, d_wl0, P.all.n, d_desc, d_mm);
+  gjk::minmax(s, d_wl0, P.all.n, d_tabs0, P.all.tn, d_desc, d_mmt, d_mm);
   std::vector<int32_t> mm((size_t)P.nt * MAXK * 2);
   if ((st = check(hipMemcpyAsync(mm.data(), d_mm, mm.size() * 4, hipMemcpyDeviceToHost, s), "key ranges"))) return st;
   if ((st = check(hipStreamSynchronize(s), "key ranges"))) return st;

@@ -69,8 +69,11 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t dig, bool valid, int bi
 }
 
 // ---------------------------------------------------------------------------
+// Per-tile column ranges (no atomics: every tile writes its own slot), then
+// one block per table reduces its tiles.
 __global__ void __launch_bounds__(GJ_BLOCK) k_minmax(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
-                                                     int32_t* __restrict__ mm) {
+                                                     int32_t* __restrict__ mmt) {
+  __shared__ int32_t sh[2][GJ_WAVES];
   const WorkItem w = wl[blockIdx.x];
   const TDesc& d = D[w.t];
   const int64_t base = (int64_t)w.tile * GJ_TILE;
@@ -91,9 +94,53 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_minmax(const WorkItem* __restrict_
       hi = max(hi, __shfl_xor(hi, o, 64));
     }
     if (lane_id() == 0) {
-      atomicMin(&mm[(w.t * MAXK + c) * 2 + 0], lo);
-      atomicMax(&mm[(w.t * MAXK + c) * 2 + 1], hi);
+      sh[0][wave_id()] = lo;
+      sh[1][wave_id()] = hi;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int v = 1; v < GJ_WAVES; ++v) {
+        lo = min(lo, sh[0][v]);
+        hi = max(hi, sh[1][v]);
+      }
+      mmt[((d.agg_off + w.tile) * MAXK + c) * 2 + 0] = lo;
+      mmt[((d.agg_off + w.tile) * MAXK + c) * 2 + 1] = hi;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(GJ_BLOCK) k_minmax_reduce(const int32_t* __restrict__ tabs,
+                                                            const TDesc* __restrict__ D,
+                                                            const int32_t* __restrict__ mmt, int32_t* __restrict__ mm) {
+  __shared__ int32_t sh[2][GJ_WAVES];
+  const int t = tabs[blockIdx.x];
+  const TDesc& d = D[t];
+  for (int c = 0; c < d.k; ++c) {
+    int32_t lo = INT32_MAX, hi = INT32_MIN;
+    for (int64_t i = threadIdx.x; i < d.ntiles; i += GJ_BLOCK) {
+      lo = min(lo, mmt[((d.agg_off + i) * MAXK + c) * 2 + 0]);
+      hi = max(hi, mmt[((d.agg_off + i) * MAXK + c) * 2 + 1]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = min(lo, __shfl_xor(lo, o, 64));
+      hi = max(hi, __shfl_xor(hi, o, 64));
+    }
+    if (lane_id() == 0) {
+      sh[0][wave_id()] = lo;
+      sh[1][wave_id()] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int v = 1; v < GJ_WAVES; ++v) {
+        lo = min(lo, sh[0][v]);
+        hi = max(hi, sh[1][v]);
+      }
+      mm[(t * MAXK + c) * 2 + 0] = lo;
+      mm[(t * MAXK + c) * 2 + 1] = hi;
+    }
+    __syncthreads();
   }
 }
 
@@ -417,8 +464,10 @@ void fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v0, int32_t v1) {
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(GJ_BLOCK), 0, s, p, n, v0, v1);
 }
 
-void minmax(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, int32_t* mm) {
-  if (nwl > 0) hipLaunchKernelGGL(k_minmax, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, mm);
+void minmax(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,
+            int32_t* mmt, int32_t* mm) {
+  if (nwl > 0) hipLaunchKernelGGL(k_minmax, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, mmt);
+  if (ntab > 0) hipLaunchKernelGGL(k_minmax_reduce, dim3(ntab), dim3(GJ_BLOCK), 0, s, tabs, D, mmt, mm);
 }
 
 void pack(hipStream_t s, int wide, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& P) {

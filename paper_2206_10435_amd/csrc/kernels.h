@@ -7,7 +7,9 @@ namespace gjk {
 
 // factor.hip
 void fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v0, int32_t v1);
-void minmax(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, int32_t* mm);
+// per-column ranges: per-tile partials into mmt (agg_slots x MAXK x 2), reduced per table into mm
+void minmax(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,
+            int32_t* mmt, int32_t* mm);
 void pack(hipStream_t s, int wide, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& P);
 void radix_pass(hipStream_t s, int wide, int items, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab,
                 const TDesc* D, const FPtrs& P, int pass);

@@ -167,54 +167,64 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_up_scan(const WorkItem* __restrict
   }
 }
 
-// Downward messages into the children of the tables in the work list.
+// Downward messages into the children of the tables in the work list.  The
+// terms of one tile are first summed per child group in an LDS hash table
+// (linear probing; a key that finds no slot goes straight to global memory),
+// so a heavily shared separator value costs one global atomic per tile
+// instead of one per parent entry.
+#define DOWN_HASH 2048
 __global__ void __launch_bounds__(GJ_BLOCK) k_down(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
                                                    FPtrs F, SPtrs S) {
+  __shared__ int32_t hkey[DOWN_HASH];
+  __shared__ unsigned long long hval[DOWN_HASH];
   const WorkItem w = wl[blockIdx.x];
   const TDesc& d = D[w.t];
   const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
   const int64_t base = (int64_t)w.tile * GJ_TILE;
   if (base >= M) return;
-  for (int r = 0; r < GJ_ROUNDS; ++r) {
-    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
-    if (e >= M) break;
-    const int64_t se = d.off + e;
-    const uint64_t U = (uint64_t)S.U[se];
-    if (U == 0) continue;
-    const uint64_t Dp = d.is_root ? 1ULL : (uint64_t)S.Dg[d.off + F.egrp[se]];
-    if (Dp == 0) continue;
-    const uint64_t c = (uint64_t)(F.eend[se] - F.estart[se]);
-    const uint64_t b = smul(c, Dp);
-    uint64_t m[MAXC];
-    int32_t j[MAXC];
-#pragma unroll
-    for (int i = 0; i < MAXC; ++i) {
-      m[i] = 1;
-      j[i] = 0;
-      if (i < d.nchild) {
+  for (int ci = 0; ci < d.nchild; ++ci) {
+    const TDesc& dt = D[d.child[ci]];
+    for (int i = threadIdx.x; i < DOWN_HASH; i += GJ_BLOCK) {
+      hkey[i] = -1;
+      hval[i] = 0;
+    }
+    __syncthreads();
+    for (int r = 0; r < GJ_ROUNDS; ++r) {
+      const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+      if (e >= M) break;
+      const int64_t se = d.off + e;
+      const uint64_t U = (uint64_t)S.U[se];
+      if (U == 0) continue;
+      const uint64_t Dp = d.is_root ? 1ULL : (uint64_t)S.Dg[d.off + F.egrp[se]];
+      if (Dp == 0) continue;
+      const uint64_t c = (uint64_t)(F.eend[se] - F.estart[se]);
+      // c * Dp * product of the other children's messages
+      uint64_t term = smul(c, Dp);
+      for (int i = 0; i < d.nchild; ++i) {
+        if (i == ci) continue;
         const TDesc& dc = D[d.child[i]];
-        j[i] = S.link[dc.link_off + e];
-        m[i] = (uint64_t)S.Mg[dc.off + j[i]];
+        term = smul(term, (uint64_t)S.Mg[dc.off + S.link[dc.link_off + e]]);
       }
-    }
-    // product of all the other children's messages: prefix * suffix
-    uint64_t pre[MAXC];
-    uint64_t acc = 1;
-#pragma unroll
-    for (int i = 0; i < MAXC; ++i) {
-      pre[i] = acc;
-      acc = smul(acc, m[i]);
-    }
-    acc = 1;
-#pragma unroll
-    for (int i = MAXC - 1; i >= 0; --i) {
-      if (i < d.nchild) {
-        const TDesc& dc = D[d.child[i]];
-        const uint64_t term = smul(b, smul(pre[i], acc));
-        atomicAdd((unsigned long long*)(S.Dg + dc.off + j[i]), (unsigned long long)term);
+      const int32_t j = S.link[dt.link_off + e];
+      uint32_t h = ((uint32_t)j * 2654435761u) >> 21;  // 11 bits
+      bool placed = false;
+#pragma unroll 1
+      for (int p = 0; p < 8 && !placed; ++p) {
+        const uint32_t slot = (h + p) & (DOWN_HASH - 1);
+        const int32_t prev = atomicCAS(&hkey[slot], -1, j);
+        if (prev == -1 || prev == j) {
+          atomicAdd(&hval[slot], (unsigned long long)term);
+          placed = true;
+        }
       }
-      acc = smul(acc, m[i]);
+      if (!placed) atomicAdd((unsigned long long*)(S.Dg + dt.off + j), (unsigned long long)term);
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < DOWN_HASH; i += GJ_BLOCK) {
+      const int32_t j = hkey[i];
+      if (j >= 0) atomicAdd((unsigned long long*)(S.Dg + dt.off + j), hval[i]);
+    }
+    __syncthreads();
   }
 }
 

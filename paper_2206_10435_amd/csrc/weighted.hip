@@ -1,23 +1,344 @@
-// Weighted join and its adjoint -- not implemented yet.
+// Weighted join size and its adjoint.
+//
+// Every row r of table t carries a weight w_t(r); the weighted join size is
+// W = sum over result tuples of the product of their rows' weights, which is
+// the partition function of Eq. 3 with each table's potential holding the
+// summed weights of an entry's rows instead of its row count (Sec. 3.2
+// potentials, generalized).  So:
+//   forward   cw(e) = sum of w over e's rows; the upward pass of Algorithm 2 in
+//             float64: Uw(e) = prod of the children's messages at e,
+//             Mw(s) = sum over entries with separator s of cw * Uw,
+//             W = sum over root entries of cw * Uw.
+//   backward  W is linear in each weight, dW/dw_t(r) = Uw(e(r)) * Dw(e(r))
+//             where Dw is the downward message (the conditioning of
+//             Algorithms 3-4) computed with cw in place of c:
+//             Dw_t(s) = sum over parent entries e' with e'[col] = s of
+//             cw(e') * Dw_p(e') * prod of the siblings' messages; Dw = 1 at
+//             the root.  This is the adjoint of the forward pass: one
+//             downward sweep yields the gradient of every weight.
+// Sums over a group run per wavefront (entries of a group are contiguous) and
+// one float64 atomic per run; downward terms are summed per tile in an LDS
+// hash table first.  At unit weights every value is an integer below 2^53,
+// so every order of summation gives the exact integer counts.
+#include <vector>
+
+#include "kernels.h"
 #include "plan.h"
 
 using namespace gjh;
 
 struct gj_wstate {
-  int dummy;
+  gj_ctx* ctx = nullptr;
+  gj_factors* f = nullptr;
+  Arena arena;
+  double* cw = nullptr;   // per entry slot: summed weights
+  double* Uw = nullptr;   // per entry slot
+  double* Mw = nullptr;   // per group slot
+  double* Dw = nullptr;   // per group slot
+  int32_t* link = nullptr;  // per parent entry, per child (link regions)
+  double* W = nullptr;
+  std::vector<const void*> w;  // weights (borrowed; must stay valid until backward)
+  int dtype = 1;
+  explicit gj_wstate(gj_ctx* c) : arena(c) {}
 };
+
+namespace {
+
+__device__ __forceinline__ int32_t find_sorted_w(const int32_t* __restrict__ a, int64_t n, int32_t v) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < n && a[lo] == v) ? (int32_t)lo : -1;
+}
+
+struct WPtrs {
+  const void* w[GJ_MAX_TABLES];  // per table (weighted factors hold one query)
+  double* cw;
+  double* Uw;
+  double* Mw;
+  double* Dw;
+  int32_t* link;
+  double* W;
+  int dtype;  // 0 f32, 1 f64
+};
+
+__device__ __forceinline__ double wget(const WPtrs& P, int t, int64_t r) {
+  return P.dtype ? reinterpret_cast<const double*>(P.w[t])[r] : (double)reinterpret_cast<const float*>(P.w[t])[r];
+}
+
+// Per entry: summed weights of its rows.
+__global__ void __launch_bounds__(GJ_BLOCK) k_wcount(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
+                                                     FPtrs F, WPtrs P) {
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+    if (e >= M) break;
+    const int64_t se = d.off + e;
+    double s = 0.0;
+    for (int32_t i = F.estart[se]; i < F.eend[se]; ++i) s += wget(P, w.t, F.perm[d.off + i]);
+    P.cw[se] = s;
+  }
+}
+
+// Upward step for the tables of one height: Uw, links, and the group sums Mw
+// (zeroed beforehand) by one atomic per run of equal groups in a wavefront.
+__global__ void __launch_bounds__(GJ_BLOCK) k_wup(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
+                                                  FPtrs F, WPtrs P) {
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  if (base >= M) return;
+  const int ln = lane_id();
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+    const bool valid = e < M;
+    const int64_t se = d.off + e;
+    double cu = 0.0;
+    int32_t g = -1;
+    if (valid) {
+      double U = 1.0;
+      for (int i = 0; i < d.nchild; ++i) {
+        const int ch = d.child[i];
+        const TDesc& dc = D[ch];
+        const int32_t v = F.ekey[d.key_off + (int64_t)d.child_col[i] * d.n + e];
+        const int32_t j = find_sorted_w(F.gval + dc.off, F.cnt[ch * CNT_STRIDE + CNT_G], v);
+        P.link[dc.link_off + e] = j;
+        U *= j >= 0 ? P.Mw[dc.off + j] : 0.0;
+      }
+      P.Uw[se] = U;
+      cu = P.cw[se] * U;
+      g = F.egrp[se];
+    }
+    // segmented sum over runs of equal g inside the wavefront
+    const int32_t gprev = __shfl_up(g, 1, 64);
+    uint32_t head = (ln == 0 || gprev != g) ? 1u : 0u;
+    double v = cu;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double y = __shfl_up(v, o, 64);
+      const uint32_t hy = __shfl_up(head, o, 64);
+      if (ln >= o && !head) v += y;
+      if (ln >= o) head |= hy;
+    }
+    const int32_t gnext = __shfl_down(g, 1, 64);
+    const bool last = ln == 63 || gnext != g;
+    if (valid && last) {
+      if (d.is_root)
+        atomicAdd(P.W, v);
+      else
+        atomicAdd(P.Mw + d.off + g, v);
+    }
+  }
+}
+
+#define WDOWN_HASH 2048
+// Downward step into the children of the tables in the work list.
+__global__ void __launch_bounds__(GJ_BLOCK) k_wdown(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
+                                                    FPtrs F, WPtrs P) {
+  __shared__ int32_t hkey[WDOWN_HASH];
+  __shared__ double hval[WDOWN_HASH];
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  if (base >= M) return;
+  for (int ci = 0; ci < d.nchild; ++ci) {
+    const TDesc& dt = D[d.child[ci]];
+    for (int i = threadIdx.x; i < WDOWN_HASH; i += GJ_BLOCK) {
+      hkey[i] = -1;
+      hval[i] = 0.0;
+    }
+    __syncthreads();
+    for (int r = 0; r < GJ_ROUNDS; ++r) {
+      const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+      if (e >= M) break;
+      const int64_t se = d.off + e;
+      const int32_t j = P.link[dt.link_off + e];
+      if (j < 0) continue;
+      const double Dp = d.is_root ? 1.0 : P.Dw[d.off + F.egrp[se]];
+      double term = P.cw[se] * Dp;
+      for (int i = 0; i < d.nchild; ++i) {
+        if (i == ci) continue;
+        const TDesc& dc = D[d.child[i]];
+        const int32_t jj = P.link[dc.link_off + e];
+        term *= jj >= 0 ? P.Mw[dc.off + jj] : 0.0;
+      }
+      if (term == 0.0) continue;
+      const uint32_t h = ((uint32_t)j * 2654435761u) >> 21;
+      bool placed = false;
+#pragma unroll 1
+      for (int p = 0; p < 8 && !placed; ++p) {
+        const uint32_t slot = (h + p) & (WDOWN_HASH - 1);
+        const int32_t prev = atomicCAS(&hkey[slot], -1, j);
+        if (prev == -1 || prev == j) {
+          atomicAdd(&hval[slot], term);
+          placed = true;
+        }
+      }
+      if (!placed) atomicAdd(P.Dw + dt.off + j, term);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < WDOWN_HASH; i += GJ_BLOCK) {
+      const int32_t j = hkey[i];
+      if (j >= 0) atomicAdd(P.Dw + dt.off + j, hval[i]);
+    }
+    __syncthreads();
+  }
+}
+
+// Per row: gradW * Uw(e) * Dw(e), written in the weight dtype.
+struct GPtrs {
+  void* g[GJ_MAX_TABLES];
+};
+
+__global__ void __launch_bounds__(GJ_BLOCK) k_wgrad(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
+                                                    FPtrs F, WPtrs P, const double* __restrict__ gW, GPtrs grad) {
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  const double g0 = *gW;
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+    if (e >= M) break;
+    const int64_t se = d.off + e;
+    const double Dv = d.is_root ? 1.0 : P.Dw[d.off + F.egrp[se]];
+    const double gv = g0 * P.Uw[se] * Dv;
+    void* gp = grad.g[w.t];
+    for (int32_t i = F.estart[se]; i < F.eend[se]; ++i) {
+      const int32_t row = F.perm[d.off + i];
+      if (P.dtype)
+        reinterpret_cast<double*>(gp)[row] = gv;
+      else
+        reinterpret_cast<float*>(gp)[row] = (float)gv;
+    }
+  }
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+void fill_f64(hipStream_t s, double* p, int64_t n, double v) {
+  if (n <= 0) return;
+  const int blocks = (int)std::min<int64_t>((n + GJ_BLOCK - 1) / GJ_BLOCK, 4096);
+  hipLaunchKernelGGL(k_fill_f64, dim3(blocks), dim3(GJ_BLOCK), 0, s, p, n, v);
+}
+
+WPtrs wptrs(const gj_wstate* st) {
+  WPtrs P{};
+  for (size_t t = 0; t < st->w.size(); ++t) P.w[t] = st->w[t];
+  P.cw = st->cw;
+  P.Uw = st->Uw;
+  P.Mw = st->Mw;
+  P.Dw = st->Dw;
+  P.link = st->link;
+  P.W = st->W;
+  P.dtype = st->dtype;
+  return P;
+}
+
+}  // namespace
 
 extern "C" {
 
-gj_status gj_weighted_forward(gj_ctx*, const gj_factors*, const void* const*, int32_t, double*, gj_wstate**) {
-  set_error("gj_weighted_forward: not implemented");
-  return GJ_E_INVALID;
+gj_status gj_weighted_forward(gj_ctx* ctx, const gj_factors* fc, const void* const* w, int32_t w_dtype, double* d_W,
+                              gj_wstate** saved) {
+  if (!ctx || !fc || !w || !d_W || !saved || (w_dtype != 0 && w_dtype != 1)) {
+    set_error("gj_weighted_forward: bad argument");
+    return GJ_E_INVALID;
+  }
+  gj_factors* f = const_cast<gj_factors*>(fc);
+  const Plan& Pl = f->plan;
+  if (Pl.nq != 1) {
+    set_error("gj_weighted_forward: factors of a single query expected");
+    return GJ_E_INVALID;
+  }
+  for (int t = 0; t < Pl.nt; ++t)
+    if (Pl.ht[t].n > 0 && !w[t]) {
+      set_error("gj_weighted_forward: null weights for table %d", t);
+      return GJ_E_INVALID;
+    }
+  gj_wstate* st = new gj_wstate(ctx);
+  st->ctx = ctx;
+  st->f = f;
+  f->refs++;
+  st->w.assign(w, w + Pl.nt);
+  st->dtype = w_dtype;
+  st->cw = st->arena.get_n<double>(Pl.S);
+  st->Uw = st->arena.get_n<double>(Pl.S);
+  st->Mw = st->arena.get_n<double>(Pl.S);
+  st->Dw = st->arena.get_n<double>(Pl.S);
+  st->link = st->arena.get_n<int32_t>(Pl.link_slots);
+  st->W = st->arena.get_n<double>(1);
+  if (!st->cw || !st->Uw || !st->Mw || !st->Dw || !st->link || !st->W) {
+    gj_free_wstate(st);
+    return GJ_E_OOM;
+  }
+  hipStream_t s = ctx->stream;
+  const WPtrs P = wptrs(st);
+  fill_f64(s, st->Mw, Pl.S, 0.0);
+  fill_f64(s, st->W, 1, 0.0);
+  hipLaunchKernelGGL(k_wcount, dim3(std::max(1, Pl.all.n)), dim3(GJ_BLOCK), 0, s, Pl.d_wl + Pl.all.off, Pl.d_desc,
+                     f->F, P);
+  for (int h = 0; h <= Pl.max_height; ++h) {
+    const WL& l = Pl.up[h];
+    if (l.n > 0) hipLaunchKernelGGL(k_wup, dim3(l.n), dim3(GJ_BLOCK), 0, s, Pl.d_wl + l.off, Pl.d_desc, f->F, P);
+  }
+  gj_status stt = check(hipMemcpyAsync(d_W, st->W, 8, hipMemcpyDeviceToDevice, s), "weighted forward");
+  if (!stt) stt = check(hipGetLastError(), "weighted forward kernels");
+  if (stt) {
+    gj_free_wstate(st);
+    return stt;
+  }
+  *saved = st;
+  return GJ_OK;
 }
-gj_status gj_weighted_backward(gj_ctx*, const gj_wstate*, const double*, void* const*) {
-  set_error("gj_weighted_backward: not implemented");
-  return GJ_E_INVALID;
+
+gj_status gj_weighted_backward(gj_ctx* ctx, const gj_wstate* stc, const double* d_gradW, void* const* grad_w) {
+  if (!ctx || !stc || !d_gradW || !grad_w) {
+    set_error("gj_weighted_backward: bad argument");
+    return GJ_E_INVALID;
+  }
+  gj_wstate* st = const_cast<gj_wstate*>(stc);
+  const Plan& Pl = st->f->plan;
+  for (int t = 0; t < Pl.nt; ++t)
+    if (Pl.ht[t].n > 0 && !grad_w[t]) {
+      set_error("gj_weighted_backward: null gradient buffer for table %d", t);
+      return GJ_E_INVALID;
+    }
+  hipStream_t s = ctx->stream;
+  const WPtrs P = wptrs(st);
+  GPtrs G{};
+  for (int t = 0; t < Pl.nt; ++t) G.g[t] = grad_w[t];
+  fill_f64(s, st->Dw, Pl.S, 0.0);
+  for (int dd = 1; dd <= Pl.max_depth; ++dd) {
+    const WL& l = Pl.down[dd];
+    if (l.n > 0) hipLaunchKernelGGL(k_wdown, dim3(l.n), dim3(GJ_BLOCK), 0, s, Pl.d_wl + l.off, Pl.d_desc, st->f->F, P);
+  }
+  if (Pl.all.n > 0)
+    hipLaunchKernelGGL(k_wgrad, dim3(Pl.all.n), dim3(GJ_BLOCK), 0, s, Pl.d_wl + Pl.all.off, Pl.d_desc, st->f->F, P,
+                       d_gradW, G);
+  return check(hipGetLastError(), "weighted backward kernels");
 }
-void gj_free_wstate(gj_wstate* st) { delete st; }
+
+void gj_free_wstate(gj_wstate* st) {
+  if (!st) return;
+  gj_factors* f = st->f;
+  st->arena.release();
+  delete st;
+  if (f) gj_free_factors(f);
+}
 
 gj_status gj_unroll_gfjs(gj_ctx*, const gj_summary*, int64_t, int64_t, int32_t* const*, int64_t* const*, int64_t*) {
   set_error("gj_unroll_gfjs: not implemented");
