@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--chunks", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tuples", type=int, default=100_000_000)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="after the timed steps, copy 1 GiB once (a plain copy of known size for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU: the path is single-GPU "
@@ -161,6 +163,14 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
     value = tuples_per_step / (ms_per_step / 1000.0)
+
+    if args.calibrate:
+        src = torch.empty(1 << 27, dtype=torch.int64, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     durs = [a.elapsed_time(b) for a, b in exp_ms]
     # full chunks only, for a per-launch figure of the dominant kernel
