@@ -89,6 +89,9 @@ struct State {
   std::vector<std::vector<i128>> down, up;
   std::vector<std::unordered_map<int32_t, i128>> sumdown, upval;
   i128 Q = 0;
+  // the root's group-by, computed once on first use by rank/unrank
+  std::map<std::vector<int32_t>, std::vector<int32_t>> root_groups;
+  bool root_grouped = false;
 
   int32_t key(int t, int c, int64_t r) const { return col[t][c][r]; }
 
@@ -243,14 +246,21 @@ bool dfs(const State& s, int t, std::vector<int32_t>& rows, Emitter& em) {
 
 // Candidate entries of table t below the chosen prefix: rows whose separator
 // matches the parent's chosen row, grouped by key tuple (canonical order).
-std::map<std::vector<int32_t>, std::vector<int32_t>> candidates(const State& s, int t,
-                                                                 const std::vector<int32_t>& rep) {
-  std::map<std::vector<int32_t>, std::vector<int32_t>> g;
-  if (t == 0) return group_by(s, 0);
+// For the root these are all its rows; that grouping is kept in the state.
+typedef std::map<std::vector<int32_t>, std::vector<int32_t>> Groups;
+const Groups& candidates(State& s, int t, const std::vector<int32_t>& rep, Groups& scratch) {
+  if (t == 0) {
+    if (!s.root_grouped) {
+      s.root_groups = group_by(s, 0);
+      s.root_grouped = true;
+    }
+    return s.root_groups;
+  }
+  scratch.clear();
   auto it = s.by_sep[t].find(s.key(s.par[t], s.pcol[t], rep[s.par[t]]));
-  if (it == s.by_sep[t].end()) return g;
-  for (int32_t r : it->second) g[s.canon_key(t, r)].push_back(r);
-  return g;
+  if (it == s.by_sep[t].end()) return scratch;
+  for (int32_t r : it->second) scratch[s.canon_key(t, r)].push_back(r);
+  return scratch;
 }
 
 // Number of result tuples whose value groups for tables 0..t are fixed to
@@ -455,8 +465,9 @@ int orc_unrank(void* h, int64_t R, int32_t* tuple) {
   std::vector<int32_t> rep(n);
   std::vector<int64_t> gsize(n);
   std::vector<std::vector<int32_t>> grows(n);
+  Groups scratch;
   for (int t = 0; t < n; ++t) {
-    auto cand = candidates(s, t, rep);
+    const Groups& cand = candidates(s, t, rep, scratch);
     bool found = false;
     for (auto& kv : cand) {
       rep[t] = kv.second[0];
@@ -489,8 +500,9 @@ int orc_rank(void* h, const int32_t* tuple, int64_t* R) {
   std::vector<int32_t> rep(n);
   std::vector<int64_t> gsize(n);
   std::vector<int64_t> pos(n);
+  Groups scratch;
   for (int t = 0; t < n; ++t) {
-    auto cand = candidates(s, t, rep);
+    const Groups& cand = candidates(s, t, rep, scratch);
     std::vector<int32_t> mine = s.canon_key(t, tuple[t]);
     for (auto& kv : cand) {
       rep[t] = kv.second[0];

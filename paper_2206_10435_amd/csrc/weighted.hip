@@ -340,9 +340,5 @@ void gj_free_wstate(gj_wstate* st) {
   if (f) gj_free_factors(f);
 }
 
-gj_status gj_unroll_gfjs(gj_ctx*, const gj_summary*, int64_t, int64_t, int32_t* const*, int64_t* const*, int64_t*) {
-  set_error("gj_unroll_gfjs: not implemented");
-  return GJ_E_INVALID;
-}
 
 }  // extern "C"

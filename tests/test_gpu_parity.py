@@ -229,3 +229,30 @@ def test_overflow_reported(gctx, oracle_mod):
     with pytest.raises(gj.GJError) as ei:
         gctx.summarize(f)
     assert ei.value.status == gj.GJ_E_OVERFLOW
+
+
+def test_unroll_gfjs_fig1_and_ranges(gctx, oracle_mod):
+    from conftest import load_fig2
+    from paper_2206_10435_amd import gj
+
+    q = load_fig1()
+    o = oracle_mod.Oracle(q)
+    tabs = gj.to_device_tables(q)
+    s = gctx.summarize(gctx.build_factors(tabs, q.parent, q.sep_col, q.parent_col))
+    runs = gctx.unroll_gfjs(s, 0, 32)
+    gfjs, _, _ = load_fig2()
+    for col, (vals, freqs) in zip("ABCD", runs):
+        assert list(zip(vals.tolist(), freqs.tolist())) == gfjs[col], col
+    # ranges of a larger join against the oracle's runs over the same rows
+    q = W.random_tree_query(102, 4, 6000, 1200, s=0.6, max_extra_cols=3, min_rows=2000)
+    o = oracle_mod.Oracle(q)
+    ref = o.canonical_result()
+    s = gctx.summarize(gctx.build_factors(gj.to_device_tables(q), q.parent, q.sep_col, q.parent_col))
+    Q = s.join_size
+    for first, cnt in [(0, Q), (1, 5000), (Q // 3, 70001), (Q - 10, 50)]:
+        got = gctx.unroll_gfjs(s, first, cnt)
+        exp = o.gfjs(ref[first:first + cnt])
+        assert len(got) == len(exp)
+        for (gv, gf), (ev, ef) in zip(got, exp):
+            assert np.array_equal(gv, ev) and np.array_equal(gf, ef), (first, cnt)
+            assert int(gf.sum()) == min(cnt, Q - first)

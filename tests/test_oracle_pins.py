@@ -325,3 +325,32 @@ def test_weighted_invariants_and_fd(oracle_mod):
     nz = ref != 0
     assert np.all(np.abs(fd[nz] - ref[nz]) <= 1e-13 * np.abs(ref[nz]))
     assert np.all(fd[~nz] == 0)
+
+
+def test_star_plus_chain_closed_forms(oracle_mod):
+    """Foreign keys into primary keys plus a many-to-many bridge: join size,
+    every row's fan-out and the rank of every result tuple in closed form."""
+    q = W.cfg3(fact_rows=60_000, dim_rows=(2_000, 300, 500, 700), bridge_rows=20_000, bridge_domain=1_500)
+    o = oracle_mod.Oracle(q)
+    res = o.canonical_result()
+    F, D1, B = q.tables[0], q.tables[1], q.tables[5]
+    nf, dom = q.n_rows(0), 1_500
+    cntB = np.bincount(B[0], minlength=dom).astype(np.int64)
+    d1row = np.empty(q.n_rows(1), dtype=np.int64)
+    d1row[D1[0]] = np.arange(q.n_rows(1))
+    fan_f = cntB[D1[1][d1row[F[0]]]]
+    assert o.join_size()[0] == int(fan_f.sum()) == len(res)
+    order = np.lexsort((np.arange(nf), F[3], F[2], F[1], F[0]))
+    start = np.empty(nf, dtype=np.int64)
+    start[order] = np.concatenate([[0], np.cumsum(fan_f[order])[:-1]])
+    ordB = np.argsort(B[0], kind="stable")
+    gstart = np.searchsorted(B[0][ordB], np.arange(dom))
+    pos = np.empty(q.n_rows(5), dtype=np.int64)
+    pos[ordB] = np.arange(q.n_rows(5)) - gstart[B[0][ordB]]
+    assert np.array_equal(start[res[:, 0]] + pos[res[:, 5]], np.arange(len(res)))
+    cnt_k1 = np.bincount(F[0], minlength=q.n_rows(1)).astype(np.int64)
+    assert np.array_equal(o.fanouts(0), fan_f)
+    assert np.array_equal(o.fanouts(1), cnt_k1[D1[0]] * cntB[D1[1]])
+    for i in (2, 3, 4):
+        fi = np.rint(np.bincount(F[i - 1], weights=fan_f.astype(float), minlength=q.n_rows(i))).astype(np.int64)
+        assert np.array_equal(o.fanouts(i), fi[q.tables[i][0]])
