@@ -88,6 +88,137 @@ def cpu_baseline(q, tuples: int):
     }
 
 
+def weighted_leg(ctx, torch):
+    """4-table chain, 1e6 rows, Zipf(1.2) over 1e4, weights U(0.5, 2):
+    gradients of W for every row by the adjoint (one forward + one backward)
+    against the forward-only way (re-root at each table; one factor build +
+    forward per table gives that table's gradients)."""
+    from paper_2206_10435_amd import gj
+    from paper_2206_10435_amd import workloads as W
+
+    q, w64, _ = W.cfg4()
+    dev = "cuda:0"
+    st = ctx.stream
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    tabs = gj.to_device_tables(q)
+    ws = [torch.from_numpy(w).to(dev) for w in w64]
+    f = ctx.build_factors(tabs, q.parent, q.sep_col, q.parent_col)
+    grads = [torch.empty_like(w) for w in ws]
+    gW = torch.ones((), dtype=torch.float64, device=dev)
+    for _ in range(2):  # warm-up
+        Wv, wst = ctx.weighted_forward(f, ws)
+        ctx.weighted_backward(wst, gW, grads)
+    torch.cuda.synchronize()
+    a, b, c = ev(), ev(), ev()
+    a.record(st)
+    f = ctx.build_factors(tabs, q.parent, q.sep_col, q.parent_col)
+    Wv, wst = ctx.weighted_forward(f, ws)
+    b.record(st)
+    ctx.weighted_backward(wst, gW, grads)
+    c.record(st)
+    torch.cuda.synchronize()
+    fwd_ms, bwd_ms = a.elapsed_time(b), b.elapsed_time(c)
+    # forward-only: re-root at every table
+    fo_ms = 0.0
+    worst = 0.0
+    for r in range(q.n_tables):
+        qr, order = W.reroot(q, r)
+        tr = [tabs[t] for t in order]
+        wr = [ws[t] for t in order]
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record(st)
+        fr = ctx.build_factors(tr, qr.parent, qr.sep_col, qr.parent_col)
+        Wr, sr = ctx.weighted_forward(fr, wr)
+        b.record(st)
+        torch.cuda.synchronize()
+        fo_ms += a.elapsed_time(b)
+        # the root's gradients are the forward pass's U; read them through the adjoint call
+        gr = [torch.empty_like(w) for w in wr]
+        ctx.weighted_backward(sr, gW, gr)
+        rel = float(((gr[0] - grads[r]).abs() / grads[r].abs().clamp_min(1e-300)).max())
+        worst = max(worst, rel, abs(float(Wr) - float(Wv)) / float(Wv))
+    return {
+        "workload": "wchain4_N1e6_D1e4_zipf1.2_w~U(0.5,2)_f64",
+        "W": float(Wv),
+        "build_plus_forward_ms": fwd_ms,
+        "adjoint_backward_ms": bwd_ms,
+        "all_gradients_adjoint_ms": fwd_ms + bwd_ms,
+        "all_gradients_forward_only_ms": fo_ms,
+        "speedup": fo_ms / (fwd_ms + bwd_ms),
+        "max_rel_diff_vs_forward_only": worst,
+    }
+
+
+def batch_leg(ctx, torch, tune: bool):
+    """256 independent queries (2-6 tables, chain or star, 1e3-1e6 rows
+    log-uniform, Zipf s in [0, 1.5] over 1e2-1e5 values): one recorded graph
+    against the same queries launched one at a time."""
+    import time as _t
+
+    from paper_2206_10435_amd import autotune, gj
+    from paper_2206_10435_amd import workloads as W
+
+    qs = W.cfg5()
+    qd = [dict(tables=gj.to_device_tables(q), parent=q.parent, sep_col=q.sep_col, parent_col=q.parent_col)
+          for q in qs]
+    rows = sum(q.total_rows() for q in qs)
+    if tune:
+        tb = autotune.tune_batch(ctx, qd)
+        b, chosen = tb["batch"], {k: tb[k] for k in ("sort_items", "radix_bits")}
+    else:
+        b, chosen = ctx.batch_create(qd), {"sort_items": 16, "radix_bits": 8}
+    for _ in range(2):
+        b.launch(graph=True)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = _t.perf_counter()
+    for _ in range(reps):
+        b.launch(graph=True)
+    torch.cuda.synchronize()
+    graph_ms = (_t.perf_counter() - t0) * 1000 / reps
+    t0 = _t.perf_counter()
+    for _ in range(reps):
+        b.launch(graph=False)
+    torch.cuda.synchronize()
+    eager_ms = (_t.perf_counter() - t0) * 1000 / reps
+    js, stt = b.results()
+    # one query at a time: factor build + summary per query
+    sizes, t_one = [], 0.0
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        sz = []
+        for q in qd:
+            f = ctx.build_factors(q["tables"], q["parent"], q["sep_col"], q["parent_col"])
+            try:
+                sz.append(ctx.summarize(f).join_size)
+            except gj.GJError as e:
+                sz.append(-e.status)
+        torch.cuda.synchronize()
+        t_one = (_t.perf_counter() - t0) * 1000
+        sizes = sz
+    same = all((st == gj.GJ_OK and j == s2) or (st == gj.GJ_E_OVERFLOW and s2 == -gj.GJ_E_OVERFLOW)
+               for j, st, s2 in zip(js, stt, sizes))
+    return {
+        "workload": "256 queries, 2-6 tables, 1e3-1e6 rows, Zipf s~U[0,1.5], domains 1e2-1e5",
+        "queries": len(qs),
+        "tables": sum(q.n_tables for q in qs),
+        "rows": rows,
+        "overflowing_queries": int((stt == gj.GJ_E_OVERFLOW).sum()),
+        "tune": chosen,
+        "graph_ms": graph_ms,
+        "eager_batched_ms": eager_ms,
+        "one_at_a_time_ms": t_one,
+        "speedup_vs_one_at_a_time": t_one / graph_ms,
+        "rows_per_s_graph": rows / (graph_ms / 1000),
+        "identical_results": bool(same),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +228,8 @@ def main():
     ap.add_argument("--chunks", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tuples", type=int, default=100_000_000)
+    ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    ap.add_argument("--extras", action="store_true", help="also time the weighted adjoint and the 256-query batch")
     ap.add_argument("--calibrate", action="store_true",
                     help="after the timed steps, copy 1 GiB once (a plain copy of known size for counter scaling)")
     args = ap.parse_args()
@@ -127,6 +260,13 @@ def main():
     chunk_rows = [min(CHUNK, Q - c * CHUNK) for c in range(nchunks)]
     tuples_per_step = int(sum(chunk_rows))
     out = torch.empty(CHUNK * n, dtype=torch.int64, device=dev)
+    tune_rec = None
+    if args.tune:
+        from paper_2206_10435_amd import autotune
+
+        ft = autotune.tune_factors(ctx, tabs, q.parent, q.sep_col, q.parent_col)
+        dt = autotune.tune_desummarize(ctx, s, out, 0, chunk_rows[0], ft["sort_items"], ft["radix_bits"])
+        tune_rec = autotune.apply(ctx, ft, dt)
     del f, s
     torch.cuda.synchronize()
 
@@ -216,6 +356,13 @@ def main():
             "traffic": traffic,
         },
     }
+    if tune_rec is not None:
+        rec["tune"] = tune_rec
+    if args.extras:
+        del out
+        torch.cuda.empty_cache()
+        rec["weighted"] = weighted_leg(ctx, torch)
+        rec["batch"] = batch_leg(ctx, torch, args.tune)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(q, args.cpu_tuples)
     print(json.dumps(rec), flush=True)

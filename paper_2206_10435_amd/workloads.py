@@ -134,6 +134,32 @@ def star_query(seed: int, cfg: int, n_tables: int, n_rows, domain: int, s: float
     return Query(name, tables, parent, sep, pcol)
 
 
+def reroot(q: Query, r: int):
+    """The same query with table r as the root: tables reordered breadth-first
+    from r so that every parent precedes its children.  Returns the query and
+    the old index of every new table."""
+    n = q.n_tables
+    adj = [[] for _ in range(n)]  # (neighbour, my column, its column)
+    for t in range(1, n):
+        p = q.parent[t]
+        adj[t].append((p, q.sep_col[t], q.parent_col[t]))
+        adj[p].append((t, q.parent_col[t], q.sep_col[t]))
+    order, par = [r], {r: (-1, 0, 0)}
+    i = 0
+    while i < len(order):
+        u = order[i]
+        i += 1
+        for v, ucol, vcol in adj[u]:
+            if v not in par:
+                par[v] = (u, vcol, ucol)
+                order.append(v)
+    pos = {t: k for k, t in enumerate(order)}
+    parent = [-1 if par[t][0] < 0 else pos[par[t][0]] for t in order]
+    sep_col = [par[t][1] for t in order]
+    parent_col = [par[t][2] for t in order]
+    return Query(q.name + f"_root{r}", [q.tables[t] for t in order], parent, sep_col, parent_col), order
+
+
 # ---------------------------------------------------------------------------
 # The five workload shapes.
 # ---------------------------------------------------------------------------

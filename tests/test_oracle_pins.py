@@ -354,3 +354,22 @@ def test_star_plus_chain_closed_forms(oracle_mod):
     for i in (2, 3, 4):
         fi = np.rint(np.bincount(F[i - 1], weights=fan_f.astype(float), minlength=q.n_rows(i))).astype(np.int64)
         assert np.array_equal(o.fanouts(i), fi[q.tables[i][0]])
+
+
+def test_reroot_invariance(oracle_mod):
+    """Any table can be the root: join size, weighted size and every row's
+    gradient are unchanged (only the result order changes)."""
+    q = W.random_tree_query(41, 5, 400, 30, s=0.7, max_extra_cols=1, min_rows=200)
+    rng = np.random.default_rng(2)
+    w = [rng.uniform(0.5, 2.0, q.n_rows(t)) for t in range(q.n_tables)]
+    o = oracle_mod.Oracle(q)
+    W0, g0 = o.weighted(w)
+    for r in range(q.n_tables):
+        qr, order = W.reroot(q, r)
+        orr = oracle_mod.Oracle(qr)
+        assert orr.join_size() == o.join_size()
+        Wr, gr = orr.weighted([w[t] for t in order])
+        assert abs(Wr - W0) <= 1e-13 * W0
+        for k, t in enumerate(order):
+            assert np.allclose(gr[k], g0[t], rtol=1e-13, atol=0)
+            assert np.array_equal(orr.fanouts(k), o.fanouts(t))
