@@ -431,11 +431,11 @@ gj_status alloc_summary(const Plan& P, Arena& A, SPtrs& S) {
   S.cghi = A.get_n<int32_t>(P.S);
   S.clink = A.get_n<int32_t>(P.link_slots);
   S.ccs = A.get_n<int2>(P.S);
-  S.clr = A.get_n<int2>(P.link_slots);
+  S.crec = A.get_n<ChildRec>(P.link_slots);
   S.qsize = A.get_n<int64_t>(P.nq);
   S.qstatus = A.get_n<int32_t>(P.nq);
   void* all[] = {S.U,  S.pre,    S.Mg,    S.Dg,  S.link, S.e2c,  S.g2c,  S.ckey,  S.cc,    S.cU,   S.cD,
-                 S.cF, S.cpre,   S.cstart, S.cgval, S.cgM, S.cgD,  S.cglo, S.cghi, S.clink, S.qsize, S.qstatus, S.ccs, S.clr};
+                 S.cF, S.cpre,   S.cstart, S.cgval, S.cgM, S.cgD,  S.cglo, S.cghi, S.clink, S.qsize, S.qstatus, S.ccs, S.crec};
   for (void* p : all)
     if (!p) return GJ_E_OOM;
   return GJ_OK;
@@ -490,7 +490,7 @@ gj_status gj_ctx_create(int device, void* hip_stream, gj_alloc_fn alloc, gj_free
   c->user = user;
   c->tune.sort_items = 16;
   c->tune.radix_bits = 8;
-  c->tune.desum_rounds = 16;
+  c->tune.desum_rounds = 8;
   c->tune.desum_stage = 4;
   *out = c;
   return GJ_OK;
@@ -705,15 +705,9 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
     const TDesc& d = P.td[base + t];
     gjk::DTab& T = a.tab[t];
     T.perm = s->f->F.perm + d.off;
-    T.cc = s->S.cc + d.off;
-    T.cstart = s->S.cstart + d.off;
     T.cpre = s->S.cpre + d.off;
-    T.clink = d.parent >= 0 ? s->S.clink + d.link_off : nullptr;
-    T.cglo = s->S.cglo + d.off;
-    T.cghi = s->S.cghi + d.off;
-    T.cgM = s->S.cgM + d.off;
     T.ccs = s->S.ccs + d.off;
-    T.clr = d.parent >= 0 ? s->S.clr + d.link_off : nullptr;
+    T.crec = d.parent >= 0 ? s->S.crec + d.link_off : nullptr;
     T.parent = d.parent >= 0 ? d.parent - base : -1;
   }
   a.first = first_row;

@@ -28,6 +28,8 @@
 // wavefront and flushed as 16-byte units that cover whole lines.  Block
 // indices are remapped so that each XCD (own L2) expands one contiguous part
 // of the range and re-reads the same entries.
+#include <type_traits>
+
 #include "desum.h"
 #include "gj_internal.h"
 #include "kernels.h"
@@ -79,31 +81,24 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
     // ---- locate rank first + my0 ----
     uint64_t R = (uint64_t)(a.first + my0);
     uint64_t P = 1;
-    int32_t g[N];
+    int32_t lo[N];
     uint64_t mg[N];
 #pragma unroll
     for (int t = 0; t < N; ++t) {
-      g[t] = 0;
+      lo[t] = 0;
       mg[t] = 1;
     }
+    gh[0] = (int32_t)a.n_root;
 #pragma unroll
     for (int t = 0; t < N; ++t) {
       if (t < n) {
         const gjk::DTab& T = a.tab[t];
-        int64_t lo;
-        if (t == 0) {
-          lo = 0;
-          gh[t] = (int32_t)a.n_root;
-        } else {
-          lo = T.cglo[g[t]];
-          gh[t] = T.cghi[g[t]];
-        }
         uint64_t Kt = P;
 #pragma unroll
         for (int j = t + 1; j < N; ++j)
           if (j < n && a.tab[j].parent < t) Kt *= mg[j];
         // largest x in [lo, hi) with Kt * pre[x] <= R (pre[lo] == 0)
-        int64_t x0 = lo, x1 = gh[t];
+        int64_t x0 = lo[t], x1 = gh[t];
         while (x1 - x0 > 1) {
           const int64_t mid = (x0 + x1) >> 1;
           if (Kt * (uint64_t)T.cpre[mid] <= R)
@@ -117,11 +112,14 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
         c[t] = cs.x;
         st[t] = cs.y;
         P *= (uint64_t)c[t];
+        // children: their group (entry range and message) under this entry
 #pragma unroll
         for (int j = t + 1; j < N; ++j) {
           if (j < n && a.tab[j].parent == t) {
-            g[j] = a.tab[j].clink[e[t]];
-            mg[j] = (uint64_t)a.tab[j].cgM[g[j]];
+            const ChildRec rc = a.tab[j].crec[e[t]];
+            lo[j] = rc.first;
+            gh[j] = rc.end;
+            mg[j] = (uint64_t)rc.M;
           }
         }
       }
@@ -133,13 +131,24 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
         R /= (uint64_t)c[t];
       }
     }
-    GJ_CW_FILL();
+    cwb = e[tl] - CW;  // the counts window is read on the first advance inside the group
   }
 
   const int wv = wave_id();
   WT* wlds = reinterpret_cast<WT*>(lds_raw) + (int64_t)wv * 64 * KS * n;
-  int32_t* lds_cnt = reinterpret_cast<int32_t*>(lds_raw + (size_t)GJ_BLOCK * KS * n * sizeof(WT)) + wv * 64;
+  // A lane's staged round is one segment of KS*n row ids, whole 16-byte units
+  // (the launcher picks KS so).  When the unit count is a power of two, unit
+  // u of lane l's segment is stored at unit u ^ swz(l): without it the lanes
+  // of a write instruction, one segment apart, fall into the same banks.
+  const int seg_bytes = KS * n * (int)sizeof(WT);
+  const int upl = seg_bytes >> 4;
+  const bool pow2 = (upl & (upl - 1)) == 0;
+  auto swz = [&](int l) -> int { return pow2 ? (((l * upl) >> 3) ^ ((l * upl) >> 4)) & (upl - 1) : 0; };
+  const int my_swz = swz(ln);
+  unsigned char* my_seg = reinterpret_cast<unsigned char*>(wlds) + (int64_t)ln * seg_bytes;
   unsigned char* dst_base = reinterpret_cast<unsigned char*>(a.out);
+  const int64_t wave_lane0 = glane - ln;
+  const int64_t tup_bytes = (int64_t)n * (int64_t)sizeof(WT);
   const int rounds = (L + KS - 1) / KS;
   int64_t done = 0;
   for (int rd = 0; rd < rounds; ++rd) {
@@ -148,7 +157,8 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
     // chg bit (k*N + t): tuple k of the round needs a new row id for table t
     int32_t pos[KS][N];
     static_assert(KS * N <= 64, "change mask is 64 bits");
-    uint64_t chg = 0;
+    using MT = typename std::conditional<KS * N <= 32, uint32_t, uint64_t>::type;
+    MT chg = 0;
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
 #pragma unroll
@@ -162,12 +172,12 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
               carry = false;
             else
               r[t] = 0;
-            if (k + 1 < KS) chg |= 1ull << ((k + 1) * N + t);
+            if (k + 1 < KS) chg |= (MT)1 << ((k + 1) * N + t);
           }
         }
         if (carry) {
           // every row list wrapped: next entry tuple
-          if (k + 1 < KS) chg |= (N == 64 ? ~0ull : ((1ull << N) - 1)) << ((k + 1) * N);
+          if (k + 1 < KS) chg |= (MT)(((MT)1 << N) - 1) << ((k + 1) * N);
           if (e[tl] + 1 < gh[tl]) {
             // next entry of the innermost group: rows follow the current ones
             st[tl] += c[tl];
@@ -180,6 +190,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
               if (d == i) v = cw[i];
             c[tl] = v;
           } else {
+            // the deepest table with a next entry in its group advances ...
             int tc = -1;
 #pragma unroll
             for (int t = N - 1; t >= 0; --t) {
@@ -189,6 +200,16 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
               }
             }
 #pragma unroll
+            for (int t = 0; t < N; ++t) {
+              if (t < n && t == tc) {
+                const int2 cs = a.tab[t].ccs[e[t]];
+                c[t] = cs.x;
+                st[t] = cs.y;
+              }
+            }
+            // ... and every later table restarts at the first entry of the
+            // group under its parent's (possibly new) entry: one record each
+#pragma unroll
             for (int t = 1; t < N; ++t) {
               if (t < n && t > tc) {
                 const int pt = a.tab[t].parent;
@@ -196,29 +217,22 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
 #pragma unroll
                 for (int i = 0; i < N; ++i)
                   if (i == pt) ep = e[i];
-                const int2 lr = a.tab[t].clr[ep];
-                e[t] = lr.x;
-                gh[t] = lr.y;
+                const int4 rc = *reinterpret_cast<const int4*>(a.tab[t].crec + ep);
+                e[t] = rc.x;
+                gh[t] = rc.y;
+                c[t] = rc.z;
+                st[t] = rc.w;
               }
             }
-#pragma unroll
-            for (int t = 0; t < N; ++t) {
-              if (t < n && t >= tc) {
-                const int2 cs = a.tab[t].ccs[e[t]];
-                c[t] = cs.x;
-                st[t] = cs.y;
-              }
-            }
-            GJ_CW_FILL();
+            cwb = e[tl] - CW;
           }
         }
       }
     }
-    // the first tuple of a round after the lane's first round reuses the row
-    // ids of the previous round's last tuple unless they changed across the
-    // round boundary, which the previous round's control loop cannot know:
-    // gather them all for k = 0.
-    chg |= (1ull << N) - 1;
+    // the first tuple of a round gathers every row id: in the usual case the
+    // outer tables' ids are the same for all lanes of a wave, so these loads
+    // hit one line (measured faster than carrying the change bits over)
+    chg |= (MT)(((MT)1 << N) - 1);
     // ---- data: gathers of changed row ids only (exec-masked), all issued
     //      before the first use, then the round into the wave's staging ----
     int32_t v[KS][N];
@@ -226,8 +240,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
     for (int k = 0; k < KS; ++k) {
 #pragma unroll
       for (int t = 0; t < N; ++t) {
-        v[k][t] = 0;
-        if (t < n && k < kcnt && ((chg >> (k * N + t)) & 1ull)) v[k][t] = a.tab[t].perm[pos[k][t]];
+        if (t < n && k < kcnt && ((chg >> (k * N + t)) & 1)) v[k][t] = a.tab[t].perm[pos[k][t]];
       }
     }
 #pragma unroll
@@ -235,39 +248,64 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
 #pragma unroll
       for (int t = 0; t < N; ++t) {
         if (t < n) {
-          if ((chg >> (k * N + t)) & 1ull) cur[t] = v[k][t];
-          wlds[((int64_t)ln * KS + k) * n + t] = (WT)cur[t];
+          if (k < kcnt && ((chg >> (k * N + t)) & 1)) cur[t] = v[k][t];
+          const int off = (k * n + t) * (int)sizeof(WT);
+          // row ids are non-negative: zero-extended to the output width
+          *reinterpret_cast<WT*>(my_seg + ((((off >> 4) ^ my_swz)) << 4) + (off & 15)) = (WT)(uint32_t)cur[t];
         }
       }
     }
     // ---- flush: lane ln writes 16-byte units of every lane's segment ----
-    lds_cnt[ln] = kcnt;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     {
-      const int seg_bytes = KS * n * (int)sizeof(WT);
-      const int upl = seg_bytes >> 4;
       const unsigned char* src = reinterpret_cast<const unsigned char*>(wlds);
-      const int64_t wave_lane0 = glane - ln;
-      for (int q = ln; q < 64 * upl; q += 64) {
-        const int sl = q / upl;
-        const int u = q - sl * upl;
-        const int64_t bytes = (int64_t)lds_cnt[sl] * n * (int64_t)sizeof(WT);
-        const int64_t b0 = (int64_t)u * 16;
-        if (b0 >= bytes) continue;
-        const int64_t tup0 = (wave_lane0 + sl) * L + done;
-        unsigned char* dst = dst_base + tup0 * n * (int64_t)sizeof(WT) + b0;
-        const unsigned char* sp = src + (int64_t)sl * seg_bytes + b0;
-        if (b0 + 16 <= bytes) {
-          const uint4 val = *reinterpret_cast<const uint4*>(sp);
+      // every lane of the wave staged a whole round (all but the range's end)
+      const bool wave_full = (wave_lane0 + 63) * L + done + KS <= a.n_rows;
+      if (pow2 && wave_full) {
+        // unit q = ln + 64 i is unit (ln mod upl) of segment ln / upl + i * 64 / upl
+        // (swz(sl) with sl * upl = sl0 * upl + 64 i, split into its parts)
+        const int lsh = __builtin_ctz(upl);
+        const int u = ln & (upl - 1);
+        const int sl0 = ln >> lsh;
+        const int step = 64 >> lsh;
+        const int sa = (sl0 * upl) >> 3, sb = (sl0 * upl) >> 4;
+        const unsigned char* rbase = src + sl0 * seg_bytes;
+        unsigned char* dst = dst_base + ((wave_lane0 + sl0) * L + done) * tup_bytes + u * 16;
+        const int64_t dstep = (int64_t)step * L * tup_bytes;
+#pragma unroll
+        for (int i = 0; i < upl; ++i) {
+          const int sw = ((sa + 8 * i) ^ (sb + 4 * i)) & (upl - 1);
+          const uint4 val = *reinterpret_cast<const uint4*>(rbase + i * step * seg_bytes + ((u ^ sw) << 4));
           __builtin_nontemporal_store(val.x, reinterpret_cast<uint32_t*>(dst));
           __builtin_nontemporal_store(val.y, reinterpret_cast<uint32_t*>(dst) + 1);
           __builtin_nontemporal_store(val.z, reinterpret_cast<uint32_t*>(dst) + 2);
           __builtin_nontemporal_store(val.w, reinterpret_cast<uint32_t*>(dst) + 3);
-        } else {
-          for (int64_t x = 0; x < bytes - b0; x += 4)
-            *reinterpret_cast<uint32_t*>(dst + x) = *reinterpret_cast<const uint32_t*>(sp + x);
+          dst += dstep;
+        }
+      } else {
+        for (int q = ln; q < 64 * upl; q += 64) {
+          const int sl = q / upl;
+          const int u = q - sl * upl;
+          // tuples lane sl wrote this round (fewer than KS only at the end)
+          const int64_t tup0 = (wave_lane0 + sl) * L + done;
+          const int64_t scnt = max((int64_t)0, min((int64_t)KS, min((int64_t)L - done, a.n_rows - tup0)));
+          const int64_t bytes = scnt * tup_bytes;
+          const int64_t b0 = (int64_t)u * 16;
+          if (b0 >= bytes) continue;
+          unsigned char* dst = dst_base + tup0 * tup_bytes + b0;
+          const unsigned char* sp = src + (int64_t)sl * seg_bytes + ((u ^ swz(sl)) << 4);
+          if (b0 + 16 <= bytes) {
+            const uint4 val = *reinterpret_cast<const uint4*>(sp);
+            __builtin_nontemporal_store(val.x, reinterpret_cast<uint32_t*>(dst));
+            __builtin_nontemporal_store(val.y, reinterpret_cast<uint32_t*>(dst) + 1);
+            __builtin_nontemporal_store(val.z, reinterpret_cast<uint32_t*>(dst) + 2);
+            __builtin_nontemporal_store(val.w, reinterpret_cast<uint32_t*>(dst) + 3);
+          } else {
+            for (int64_t x = 0; x < bytes - b0; x += 4)
+              *reinterpret_cast<uint32_t*>(dst + x) = *reinterpret_cast<const uint32_t*>(sp + x);
+          }
         }
       }
     }
@@ -282,7 +320,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
 template <int N, typename WT>
 void launch_nw(hipStream_t s, const gjk::DesumArgs& a, int ks, int blocks) {
   if (ks == 8 && N * 8 > 64) ks = 4;  // the change mask holds KS * N bits
-  const size_t lds = (size_t)GJ_BLOCK * ks * N * sizeof(WT) + GJ_BLOCK * sizeof(int32_t);
+  const size_t lds = (size_t)GJ_BLOCK * ks * N * sizeof(WT);
   if (ks == 2) {
     hipLaunchKernelGGL((k_desum<N, WT, 2>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a);
   } else if (ks == 8) {
@@ -306,7 +344,9 @@ namespace gjk {
 
 int desummarize(hipStream_t s, const DesumArgs& a0, int rowid_bytes, int n_tables, int rounds_per_lane, int stage) {
   DesumArgs a = a0;
-  const int ks = (stage == 2 || stage == 4 || stage == 8) ? stage : 4;
+  int ks = (stage == 2 || stage == 4 || stage == 8) ? stage : 4;
+  // a lane's staged round must be whole 16-byte units (int32 ids, odd n)
+  while ((ks * n_tables * rowid_bytes) % 16 != 0) ks *= 2;
   const int rs = ks;
   if (a0.n_rows <= 0) return 0;
   if (n_tables > GJ_MAX_TABLES) return -1;

@@ -85,6 +85,16 @@ struct FPtrs {
 };
 
 // Pointers of a plan's summary arrays.
+// What the expansion needs of a child table when its parent entry changes,
+// in one 32-byte record per (child table, surviving parent entry): the child's
+// group as a range [first, end) of its surviving entries, the row count and
+// first perm position of entry `first`, and the group's upward message M.
+struct __align__(32) ChildRec {
+  int32_t first, end, c0, st0;
+  int64_t M;
+  int64_t unused;
+};
+
 struct SPtrs {
   int64_t* U;
   int64_t* pre;
@@ -107,7 +117,7 @@ struct SPtrs {
   int32_t* cghi;
   int32_t* clink;
   int2* ccs;  // surviving entry -> (row count, first position in perm)
-  int2* clr;  // surviving parent entry -> (first, end) surviving entry of the child's group
+  ChildRec* crec;  // surviving parent entry -> the child's group (see ChildRec)
   int64_t* qsize;
   int32_t* qstatus;
 };

@@ -335,8 +335,15 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_compact_links(const WorkItem* __re
         const int64_t Mch = F.cnt[d.child[i] * CNT_STRIDE + CNT_M];
         const int64_t Mcch = F.cnt[d.child[i] * CNT_STRIDE + CNT_MC];
         const int32_t glo = F.glo[dc.off + j], ghi = F.ghi[dc.off + j];
-        S.clr[dc.link_off + ci] = make_int2(glo < Mch ? S.e2c[dc.off + glo] : (int32_t)Mcch,
-                                            ghi < Mch ? S.e2c[dc.off + ghi] : (int32_t)Mcch);
+        ChildRec rc;
+        rc.first = glo < Mch ? S.e2c[dc.off + glo] : (int32_t)Mcch;
+        rc.end = ghi < Mch ? S.e2c[dc.off + ghi] : (int32_t)Mcch;
+        const int2 cs0 = rc.first < rc.end ? S.ccs[dc.off + rc.first] : make_int2(0, 0);
+        rc.c0 = cs0.x;
+        rc.st0 = cs0.y;
+        rc.M = gc >= 0 ? S.cgM[dc.off + gc] : 0;
+        rc.unused = 0;
+        S.crec[dc.link_off + ci] = rc;
       }
     }
     if (e < G) {

@@ -217,6 +217,47 @@ def test_tune_variants_same_result(gctx, oracle_mod):
         gctx.set_tune()
 
 
+def _by_table_count():
+    # one query per table count, 1..10 (10 runs the kernel built for any count)
+    specs = [(1, 300, 50000, 10), (2, 300, 3000, 100), (3, 306, 2000, 500), (4, 300, 1500, 300),
+             (5, 303, 800, 300), (6, 300, 800, 300), (7, 300, 800, 300), (8, 300, 800, 300),
+             (9, 300, 800, 300), (10, 301, 800, 300)]
+    return [W.random_tree_query(seed, n, rows, dom, s=0.7, max_extra_cols=2, min_rows=rows // 2)
+            for n, seed, rows, dom in specs]
+
+
+@pytest.mark.parametrize("q", _by_table_count(), ids=lambda q: f"n{q.n_tables}")
+def test_expansion_every_stage_width_table_count(gctx, oracle_mod, q):
+    """Every staging depth and row-id width at every table count, whole and
+    ragged ranges: covers lane segments that are not whole 16-byte units at
+    the requested depth (int32 ids, odd table counts) and the staging layouts."""
+    import torch
+
+    from paper_2206_10435_amd import gj
+
+    o = oracle_mod.Oracle(q)
+    ref = o.canonical_result().astype(np.int64)
+    tabs = gj.to_device_tables(q)
+    s = gctx.summarize(gctx.build_factors(tabs, q.parent, q.sep_col, q.parent_col))
+    Q = s.join_size
+    assert Q == len(ref) and Q > 0
+    n = q.n_tables
+    _say("case stages", q.name, "n =", n, "Q =", Q)
+    first = Q // 3 + 1
+    cnt = min(Q - first, 4097 + 13 * n)
+    try:
+        for stage in (2, 4, 8):
+            for rounds in (1, 7):
+                gctx.set_tune(16, 8, rounds, stage)
+                for dt in (torch.int32, torch.int64):
+                    got, nw = _desum(gctx, s, n, 0, Q, dt)
+                    assert nw == Q and np.array_equal(got, ref), (stage, rounds, dt)
+                    got, nw = _desum(gctx, s, n, first, cnt, dt)
+                    assert nw == cnt and np.array_equal(got, ref[first:first + cnt]), (stage, rounds, dt, "window")
+    finally:
+        gctx.set_tune()
+
+
 def test_overflow_reported(gctx, oracle_mod):
     from paper_2206_10435_amd import gj
 
