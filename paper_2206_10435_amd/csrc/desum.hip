@@ -38,6 +38,77 @@ namespace {
 
 constexpr int CW = 4;  // innermost counts read per refill
 
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Largest x in [lo, hi) with K * pre[x] <= R, where pre is strictly
+// increasing on [lo, hi) (surviving entries have c*U >= 1) and pre[lo] = 0.
+// K * pre[x] never exceeds the join size for x in [lo, hi), so no product
+// overflows.  Must be called by all 64 lanes of the wave.
+//
+// When every lane searches the same range (the usual case: a wave's targets
+// are a few thousand consecutive ranks), the wave searches it together: each
+// lane reads one of 64 evenly spaced probes, every lane finds its own slot
+// among them by a binary search over the probes held by the other lanes
+// (lane permutes, no memory), and the range shrinks to the union of the
+// lanes' slots.  That takes about log64 of the range in dependent loads
+// instead of log2.  Lanes whose targets spread over the range finish alone.
+__device__ __forceinline__ int32_t find_block(const int64_t* __restrict__ pre, int32_t lo, int32_t hi, uint64_t K,
+                                              uint64_t R, int ln) {
+  int32_t x0 = lo, x1 = hi;
+  const int32_t lo_u = __builtin_amdgcn_readfirstlane(lo);
+  const int32_t hi_u = __builtin_amdgcn_readfirstlane(hi);
+  if (__all(lo == lo_u && hi == hi_u)) {
+    int32_t L0 = lo_u, H0 = hi_u;
+    while (true) {
+      const int32_t W = H0 - L0;
+      if (W <= 1) {
+        x0 = L0;
+        x1 = L0 + 1;
+        break;
+      }
+      const bool exact = W <= 64;
+      const int32_t p = exact ? L0 + ln : L0 + (int32_t)(((int64_t)W * ln) >> 6);
+      const uint64_t v = p < H0 ? (uint64_t)pre[p] : ~0ull;
+      // slot j: the largest probe index with K * v_j <= R (probe 0 = pre[L0]
+      // qualifies for every lane, as the range holds every lane's answer)
+      int j = 0;
+#pragma unroll
+      for (int s = 32; s > 0; s >>= 1) {
+        const uint64_t vs = __shfl(v, j + s);
+        if (vs != ~0ull && K * vs <= R) j += s;
+      }
+      if (exact) {
+        x0 = L0 + j;
+        x1 = x0 + 1;
+        break;
+      }
+      x0 = L0 + (int32_t)(((int64_t)W * j) >> 6);
+      x1 = j < 63 ? L0 + (int32_t)(((int64_t)W * (j + 1)) >> 6) : H0;
+      const int32_t nL0 = wave_min_i32(x0), nH0 = wave_max_i32(x1);
+      if (nH0 - nL0 > W / 2) break;  // the lanes' targets spread out
+      L0 = nL0;
+      H0 = nH0;
+    }
+  }
+  while (x1 - x0 > 1) {
+    const int32_t mid = (int32_t)(((int64_t)x0 + x1) >> 1);
+    if (K * (uint64_t)pre[mid] <= R)
+      x0 = mid;
+    else
+      x1 = mid;
+  }
+  return x0;
+}
+
 template <int N, typename WT, int KS>
 __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -77,9 +148,12 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
     _Pragma("unroll") for (int i = 0; i < CW; ++i) cw[i] = cs[min(cwb + i, gh[tl] - 1)].x; \
   } while (0)
 
-  if (mycnt > 0) {
+  // wave-uniform: the searches below are cooperative, so every lane of a wave
+  // with any work locates (lanes past the range take the range's last rank
+  // and write nothing)
+  if ((glane - ln) * L < a.n_rows) {
     // ---- locate rank first + my0 ----
-    uint64_t R = (uint64_t)(a.first + my0);
+    uint64_t R = (uint64_t)(a.first + min(my0, a.n_rows - 1));
     uint64_t P = 1;
     int32_t lo[N];
     uint64_t mg[N];
@@ -97,16 +171,8 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
 #pragma unroll
         for (int j = t + 1; j < N; ++j)
           if (j < n && a.tab[j].parent < t) Kt *= mg[j];
-        // largest x in [lo, hi) with Kt * pre[x] <= R (pre[lo] == 0)
-        int64_t x0 = lo[t], x1 = gh[t];
-        while (x1 - x0 > 1) {
-          const int64_t mid = (x0 + x1) >> 1;
-          if (Kt * (uint64_t)T.cpre[mid] <= R)
-            x0 = mid;
-          else
-            x1 = mid;
-        }
-        e[t] = (int32_t)x0;
+        const int32_t x0 = find_block(T.cpre, lo[t], gh[t], Kt, R, ln);
+        e[t] = x0;
         R -= Kt * (uint64_t)T.cpre[x0];
         const int2 cs = T.ccs[x0];
         c[t] = cs.x;
