@@ -59,6 +59,7 @@ typedef enum {
 #define GJ_MAX_TABLES 16 /* per query */
 #define GJ_MAX_KEYS 8    /* key columns per table */
 #define GJ_MAX_CHILDREN 8
+#define GJ_MAX_OUT_COLS 16 /* value columns per materialized row */
 
 typedef struct gj_ctx gj_ctx;
 typedef struct gj_factors gj_factors;
@@ -188,6 +189,30 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
 int32_t gj_result_columns(const gj_summary* s);
 gj_status gj_unroll_gfjs(gj_ctx* ctx, const gj_summary* s, int64_t first_row, int64_t n_rows,
                          int32_t* const* values, int64_t* const* freqs, int64_t* n_runs);
+
+/* ---- value columns: payload gather in the expansion ----
+ * Materializes attribute or payload values instead of row ids (Sec. 3.6
+ * replaces every run by copies of its value).  A column set names n_cols
+ * (1..GJ_MAX_OUT_COLS) int32 device columns: column j (data[j], a host array
+ * of device pointers) holds one value per row of table tab[j], in row order --
+ * a key column or any payload column of that table.  gj_colset_create copies
+ * each column once into the factor's grouped row order (one gather through the
+ * row permutation), so the expansion reads values the way it reads row ids.
+ * The columns are borrowed for the duration of the call only.  The set holds a
+ * reference to the summary's factors; free it with gj_free_colset.  A
+ * projected summary has no rows: GJ_E_INVALID. */
+typedef struct gj_colset gj_colset;
+gj_status gj_colset_create(gj_ctx* ctx, const gj_summary* s, int32_t n_cols, const int32_t* tab,
+                           const int32_t* const* data, gj_colset** out);
+void gj_free_colset(gj_colset* cs);
+/* Rows [first_row, first_row + n_rows) of the sorted result (the order of
+ * gj_desummarize) as row-major [n_rows x n_cols] int32 values: element j of a
+ * row is column j of the set at that result row's row id of table tab[j].
+ * `out` is a 16-byte aligned device buffer; rows past the join size are not
+ * written and *n_written (host) receives the count; first_row > join size ->
+ * GJ_E_RANGE; a set made for other factors -> GJ_E_INVALID. */
+gj_status gj_desummarize_values(gj_ctx* ctx, const gj_summary* s, const gj_colset* cs, int64_t first_row,
+                                int64_t n_rows, int32_t* out, int64_t* n_written);
 
 /* ---- weighted join and its adjoint ----
  * Every row r of table t carries a weight w_t[r]; W = sum over result tuples of

@@ -682,25 +682,13 @@ int32_t gj_result_columns(const gj_summary* s) {
   return L;
 }
 
-gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, int64_t n_rows, int32_t rowid_bytes,
-                         void* out, int64_t* n_written) {
-  if (!ctx || !s || (rowid_bytes != 4 && rowid_bytes != 8) || n_rows < 0 || first_row < 0) {
-    set_error("gj_desummarize: bad argument");
-    return GJ_E_INVALID;
-  }
-  if (first_row > s->join_size) {
-    set_error("first_row %lld beyond the join size %lld", (long long)first_row, (long long)s->join_size);
-    return GJ_E_RANGE;
-  }
-  const int64_t nw = std::min(n_rows, s->join_size - first_row);
-  if (nw > 0 && (!out || ((uintptr_t)out & 15) != 0)) {
-    set_error("gj_desummarize: output must be a non-null, 16-byte aligned device buffer");
-    return GJ_E_INVALID;
-  }
+}  // extern "C"
+
+// Expansion-kernel arguments for rows [first_row, first_row + nw) of summary s.
+static void desum_args(const gj_summary* s, int64_t first_row, int64_t nw, void* out, gjk::DesumArgs& a, int& n) {
   const Plan& P = s->f->plan;
   const int base = P.qfirst[s->query];
-  const int n = P.qfirst[s->query + 1] - base;
-  gjk::DesumArgs a{};
+  n = P.qfirst[s->query + 1] - base;
   for (int t = 0; t < n; ++t) {
     const TDesc& d = P.td[base + t];
     gjk::DTab& T = a.tab[t];
@@ -714,9 +702,128 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
   a.n_rows = nw;
   a.n_root = s->cnt_host[base * CNT_STRIDE + CNT_MC];
   a.out = out;
+}
+
+extern "C" {
+
+gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, int64_t n_rows, int32_t rowid_bytes,
+                         void* out, int64_t* n_written) {
+  if (!ctx || !s || (rowid_bytes != 4 && rowid_bytes != 8) || n_rows < 0 || first_row < 0) {
+    set_error("gj_desummarize: bad argument");
+    return GJ_E_INVALID;
+  }
+  if (s->projected) {
+    set_error("gj_desummarize: a projected summary has no row ids (use gj_desummarize_projected)");
+    return GJ_E_INVALID;
+  }
+  if (first_row > s->join_size) {
+    set_error("first_row %lld beyond the join size %lld", (long long)first_row, (long long)s->join_size);
+    return GJ_E_RANGE;
+  }
+  const int64_t nw = std::min(n_rows, s->join_size - first_row);
+  if (nw > 0 && (!out || ((uintptr_t)out & 15) != 0)) {
+    set_error("gj_desummarize: output must be a non-null, 16-byte aligned device buffer");
+    return GJ_E_INVALID;
+  }
+  int n = 0;
+  gjk::DesumArgs a{};
+  desum_args(s, first_row, nw, out, a, n);
   if (nw > 0) {
     if (gjk::desummarize(ctx->stream, a, rowid_bytes, n, ctx->tune.desum_rounds, ctx->tune.desum_stage) != 0) {
       set_error("gj_desummarize: chunk too large for one launch");
+      return GJ_E_INVALID;
+    }
+    gj_status st = check(hipGetLastError(), "expansion kernel");
+    if (st) return st;
+  }
+  if (n_written) *n_written = nw;
+  return GJ_OK;
+}
+
+gj_status gj_colset_create(gj_ctx* ctx, const gj_summary* s, int32_t n_cols, const int32_t* tab,
+                           const int32_t* const* data, gj_colset** out) {
+  if (!ctx || !s || !out || n_cols < 1 || n_cols > GJ_MAX_OUT_COLS || !tab || !data) {
+    set_error("gj_colset_create: bad argument (1 <= n_cols <= %d)", GJ_MAX_OUT_COLS);
+    return GJ_E_INVALID;
+  }
+  if (s->projected) {
+    set_error("gj_colset_create: a projected summary has no row ids (use gj_desummarize_projected)");
+    return GJ_E_INVALID;
+  }
+  const Plan& P = s->f->plan;
+  const int base = P.qfirst[s->query];
+  const int n = P.qfirst[s->query + 1] - base;
+  for (int j = 0; j < n_cols; ++j) {
+    if (tab[j] < 0 || tab[j] >= n) {
+      set_error("gj_colset_create: column %d names table %d of a %d-table query", j, tab[j], n);
+      return GJ_E_INVALID;
+    }
+    if (!data[j] && P.td[base + tab[j]].n > 0) {
+      set_error("gj_colset_create: null column %d", j);
+      return GJ_E_INVALID;
+    }
+  }
+  gj_colset* c = new gj_colset(ctx);
+  c->f = s->f;
+  c->f->refs++;
+  c->query = s->query;
+  c->n_cols = n_cols;
+  for (int j = 0; j < n_cols; ++j) {
+    const TDesc& d = P.td[base + tab[j]];
+    c->tab[j] = tab[j];
+    c->col[j] = c->arena.get_n<int32_t>(d.n);
+    if (!c->col[j]) {
+      gj_free_colset(c);
+      return GJ_E_OOM;
+    }
+    gjk::gather_rows(ctx->stream, s->f->F.perm + d.off, data[j], d.n, c->col[j]);
+  }
+  gj_status st = check(hipGetLastError(), "column layout kernel");
+  if (st) {
+    gj_free_colset(c);
+    return st;
+  }
+  *out = c;
+  return GJ_OK;
+}
+
+void gj_free_colset(gj_colset* c) {
+  if (!c) return;
+  c->arena.release();
+  gj_free_factors(c->f);
+  delete c;
+}
+
+gj_status gj_desummarize_values(gj_ctx* ctx, const gj_summary* s, const gj_colset* cs, int64_t first_row,
+                                int64_t n_rows, int32_t* out, int64_t* n_written) {
+  if (!ctx || !s || !cs || n_rows < 0 || first_row < 0) {
+    set_error("gj_desummarize_values: bad argument");
+    return GJ_E_INVALID;
+  }
+  if (s->projected || cs->f != s->f || cs->query != s->query) {
+    set_error("gj_desummarize_values: the column set was made for another summary's factors");
+    return GJ_E_INVALID;
+  }
+  if (first_row > s->join_size) {
+    set_error("first_row %lld beyond the join size %lld", (long long)first_row, (long long)s->join_size);
+    return GJ_E_RANGE;
+  }
+  const int64_t nw = std::min(n_rows, s->join_size - first_row);
+  if (nw > 0 && (!out || ((uintptr_t)out & 15) != 0)) {
+    set_error("gj_desummarize_values: output must be a non-null, 16-byte aligned device buffer");
+    return GJ_E_INVALID;
+  }
+  int n = 0;
+  gjk::DesumArgs a{};
+  desum_args(s, first_row, nw, out, a, n);
+  a.n_cols = cs->n_cols;
+  for (int j = 0; j < cs->n_cols; ++j) {
+    a.col_tab[j] = cs->tab[j];
+    a.col_src[j] = cs->col[j];
+  }
+  if (nw > 0) {
+    if (gjk::desummarize(ctx->stream, a, 4, n, ctx->tune.desum_rounds, ctx->tune.desum_stage) != 0) {
+      set_error("gj_desummarize_values: chunk too large for one launch");
       return GJ_E_INVALID;
     }
     gj_status st = check(hipGetLastError(), "expansion kernel");

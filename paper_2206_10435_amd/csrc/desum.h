@@ -22,6 +22,11 @@ struct DesumArgs {
   int32_t n_tables;
   int32_t k_round;
   int32_t tuples_per_lane;
+  // value columns (n_cols = 0: row ids of every table): column j is
+  // col_src[j][position of table col_tab[j]'s row in its grouped order]
+  int32_t n_cols;
+  int32_t col_tab[GJ_MAX_OUT_COLS];
+  const int32_t* col_src[GJ_MAX_OUT_COLS];
 };
 
 

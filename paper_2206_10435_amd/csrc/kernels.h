@@ -32,5 +32,10 @@ void compact(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, in
 struct DesumArgs;
 // returns -1 if the launch does not fit one grid
 int desummarize(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables, int rounds_per_lane, int stage);
+// value columns (desum_values.hip): tuples per staging round, and the launch
+int value_round(int n_tables, int n_cols);
+void launch_values(hipStream_t s, const DesumArgs& a, int blocks);
+// out[i] = data[perm[i]] for i < n: a row-order column in grouped row order
+void gather_rows(hipStream_t s, const int32_t* perm, const int32_t* data, int64_t n, int32_t* out);
 
 }  // namespace gjk

@@ -115,5 +115,18 @@ struct gj_summary {
   bool borrowed = false;  // part of a batch: not freed by gj_free_summary
   std::vector<int64_t> cnt_host;
   int64_t join_size = 0;
+  bool projected = false;  // entries over output attributes only: no row ids
   explicit gj_summary(gj_ctx* c) : ctx(c), arena(c) {}
+};
+
+// Value columns re-laid out in a factor's grouped row order.
+struct gj_colset {
+  gj_ctx* ctx = nullptr;
+  gj_factors* f = nullptr;  // holds a reference
+  int query = 0;
+  gjh::Arena arena;
+  int n_cols = 0;
+  int tab[GJ_MAX_OUT_COLS] = {};
+  int32_t* col[GJ_MAX_OUT_COLS] = {};
+  explicit gj_colset(gj_ctx* c) : ctx(c), arena(c) {}
 };

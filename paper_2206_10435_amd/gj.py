@@ -93,6 +93,9 @@ SIGNATURES = {
     "gj_free_batch": (None, [_vp]),
     "gj_download": (C.c_int, [_vp, _vp, _vp, _sz]),
     "gj_ctx_set_tune": (C.c_int, [_vp, _vp]),
+    "gj_colset_create": (C.c_int, [_vp, _vp, _i32, _vp, _vp, _vp]),
+    "gj_free_colset": (None, [_vp]),
+    "gj_desummarize_values": (C.c_int, [_vp, _vp, _vp, _i64, _i64, _vp, _vp]),
 }
 
 
@@ -219,6 +222,33 @@ class Context:
                                      C.c_void_p(out.data_ptr()), C.byref(nw)))
         return int(nw.value)
 
+    def colset(self, s: "Summary", columns) -> "ColSet":
+        """Value columns for gj_desummarize_values: `columns` is a list of
+        (table, int32 device tensor with one value per row of that table)."""
+        tabs = np.array([int(t) for t, _ in columns], dtype=np.int32)
+        for t, c in columns:
+            if str(c.dtype) != "torch.int32" or not c.is_contiguous() or not c.is_cuda:
+                raise ValueError("value columns must be contiguous int32 device tensors")
+        ptrs = (C.c_void_p * len(columns))(*[c.data_ptr() for _, c in columns])
+        h = C.c_void_p()
+        _check(self.L.gj_colset_create(self.h, s.h, len(columns), tabs.ctypes.data_as(C.c_void_p), ptrs,
+                                       C.byref(h)))
+        return ColSet(self, h, len(columns))
+
+    def desummarize_values(self, s: "Summary", cs: "ColSet", first_row: int, n_rows: int, out) -> int:
+        """Writes rows [first_row, first_row + n_rows) as int32 values
+        (n_rows x cs.n_cols, row-major) into `out`; returns the count."""
+        import torch
+
+        if out.dtype != torch.int32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 device tensor")
+        if out.numel() < n_rows * cs.n_cols:
+            raise ValueError("out is too small")
+        nw = C.c_int64()
+        _check(self.L.gj_desummarize_values(self.h, s.h, cs.h, int(first_row), int(n_rows),
+                                            C.c_void_p(out.data_ptr()), C.byref(nw)))
+        return int(nw.value)
+
     def unroll_gfjs(self, s: "Summary", first_row: int, n_rows: int):
         """Paper-literal GFJS of a row range: list of (values, freqs) numpy pairs per result column."""
         import torch
@@ -330,6 +360,16 @@ class Summary:
         n = int(v.n)
         d = self.ctx.download
         return dict(s=d(v.s, n, np.int32), M=d(v.M, n, np.int64), D=d(v.D, n, np.int64))
+
+
+class ColSet:
+    def __init__(self, ctx: Context, h, n_cols: int):
+        self.ctx, self.h, self.n_cols = ctx, h, n_cols
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.ctx.h:
+            self.ctx.L.gj_free_colset(self.h)
+            self.h = None
 
 
 class WState:
