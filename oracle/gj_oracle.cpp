@@ -522,6 +522,106 @@ int orc_rank(void* h, const int32_t* tuple, int64_t* R) {
 }
 
 // ---------------------------------------------------------------------------
+// Early projections (Sec. 3.7): only some attributes are output attributes.
+// The projected result is the bag of the join result's tuples restricted to
+// the output attributes (every tuple keeps its multiplicity).
+//
+// mask[t] bit c marks key column c of table t as an output attribute.  A join
+// attribute is a single attribute seen from the two tables of its edge, so a
+// mark on either side counts for both.  A table is kept in the projected
+// generator if it has an output attribute besides its separator (the root: any
+// output attribute) or a kept child; every other table is deleted, i.e. only
+// its completions count.  Supported when the root is kept and every kept
+// non-root table's separator is an output attribute (otherwise two kept tables
+// would be linked through a summed-out variable).
+// Returns 0 and the normalized mask in `out`, or -1 if unsupported.
+// ---------------------------------------------------------------------------
+int orc_projection(void* h, const uint32_t* mask, uint32_t* out, int32_t* kept) {
+  State& s = *(State*)h;
+  int n = s.n;
+  std::vector<uint32_t> m(mask, mask + n);
+  for (int t = 1; t < n; ++t) {
+    bool mark = ((m[t] >> s.sep[t]) & 1u) || ((m[s.par[t]] >> s.pcol[t]) & 1u);
+    if (mark) {
+      m[t] |= 1u << s.sep[t];
+      m[s.par[t]] |= 1u << s.pcol[t];
+    }
+  }
+  std::vector<int32_t> k(n, 0);
+  for (int t = n - 1; t >= 0; --t) {
+    uint32_t own = t == 0 ? m[t] : (m[t] & ~(1u << s.sep[t]));
+    k[t] = own != 0;
+    for (int ch : s.children[t]) k[t] |= k[ch];
+  }
+  if (out) std::copy(m.begin(), m.end(), out);
+  if (kept) std::copy(k.begin(), k.end(), kept);
+  if (n == 0 || !k[0] || m[0] == 0) return -1;
+  for (int t = 1; t < n; ++t)
+    if (k[t] && !((m[t] >> s.sep[t]) & 1u)) return -1;
+  return 0;
+}
+
+// Projected entries of kept table t: the distinct values of its output
+// columns (the separator first, then the others in declared order), each with
+//   c = sum over the rows with those values of the product, over the deleted
+//       children, of the completions of the child's subtree at the row's value,
+//   U = product of the kept children's messages at the entry's values,
+//   D = completions outside t's subtree (1 at the root),
+//   F = sum of the rows' fan-outs = the number of result tuples whose t-part
+//       projects to the entry.
+// Only entries with F > 0.  Keys are written in declared order of the output
+// columns (row-major, entries x output columns).  Returns the entry count,
+// -1 if the projection is unsupported, -2 if t is deleted.
+int64_t orc_projected_table(void* h, const uint32_t* mask, int t, int32_t* keys, int64_t* c, int64_t* U, int64_t* D,
+                            int64_t* F) {
+  State& s = *(State*)h;
+  int n = s.n;
+  std::vector<uint32_t> m(n);
+  std::vector<int32_t> kept(n);
+  if (orc_projection(h, mask, m.data(), kept.data()) != 0) return -1;
+  if (!kept[t]) return -2;
+  std::vector<int> ocols;  // sort order: separator, then the others in declared order
+  if (t > 0) ocols.push_back(s.sep[t]);
+  for (int cc = 0; cc < s.K[t]; ++cc)
+    if (((m[t] >> cc) & 1u) && (t == 0 || cc != s.sep[t])) ocols.push_back(cc);
+  std::vector<int> declared;
+  for (int cc = 0; cc < s.K[t]; ++cc)
+    if ((m[t] >> cc) & 1u) declared.push_back(cc);
+  struct Acc {
+    i128 c = 0, f = 0;
+    int32_t rep = 0;
+  };
+  std::map<std::vector<int32_t>, Acc> g;
+  for (int64_t r = 0; r < s.N[t]; ++r) {
+    std::vector<int32_t> key;
+    for (int cc : ocols) key.push_back(s.key(t, cc, r));
+    i128 w = 1;
+    for (int ch : s.children[t])
+      if (!kept[ch]) w = smul(w, lookup(s.sumdown[ch], s.key(t, s.pcol[ch], r)));
+    Acc& a = g[key];
+    if (a.c == 0 && a.f == 0) a.rep = (int32_t)r;
+    a.c = sadd(a.c, w);
+    a.f = sadd(a.f, smul(s.down[t][r], s.up[t][r]));
+  }
+  int64_t e = 0;
+  for (auto& kv : g) {
+    if (kv.second.f == 0) continue;
+    int32_t r0 = kv.second.rep;
+    i128 u = 1;
+    for (int ch : s.children[t])
+      if (kept[ch]) u = smul(u, lookup(s.sumdown[ch], s.key(t, s.pcol[ch], r0)));
+    if (keys)
+      for (size_t i = 0; i < declared.size(); ++i) keys[e * (int64_t)declared.size() + i] = s.key(t, declared[i], r0);
+    if (c) c[e] = to64(kv.second.c);
+    if (U) U[e] = to64(u);
+    if (D) D[e] = to64(s.up[t][r0]);
+    if (F) F[e] = to64(kv.second.f);
+    ++e;
+  }
+  return e;
+}
+
+// ---------------------------------------------------------------------------
 // Weighted join size W = sum over result tuples of the product of their row
 // weights, and dW/dw_r, in __float128.  With all weights 1, W is the join size.
 // ---------------------------------------------------------------------------

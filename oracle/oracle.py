@@ -74,6 +74,10 @@ def lib():
         L.orc_weighted.argtypes = [vp, vp, vp]
         L.orc_weighted.restype = C.c_double
         L.orc_weighted_fd.argtypes = [vp, vp, C.c_int, vp, i64, C.c_double, C.c_int, vp]
+        L.orc_projection.argtypes = [vp, vp, vp, vp]
+        L.orc_projection.restype = C.c_int
+        L.orc_projected_table.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp]
+        L.orc_projected_table.restype = i64
         _lib = L
     return _lib
 
@@ -228,3 +232,52 @@ class Oracle:
         lib().orc_weighted_fd(self.h, _p(ptrs), int(t), _p(rows), len(rows), float(hfrac),
                               int(threads), _p(out))
         return out
+
+    # -- early projections (Sec. 3.7) ------------------------------------------
+    def projection(self, mask):
+        """(supported, normalized mask, kept flags) for output-attribute masks
+        (bit c of mask[t] = key column c of table t)."""
+        m = np.ascontiguousarray(mask, dtype=np.uint32)
+        out = np.zeros(self.n, dtype=np.uint32)
+        kept = np.zeros(self.n, dtype=np.int32)
+        rc = lib().orc_projection(self.h, _p(m), _p(out), _p(kept))
+        return rc == 0, out, kept.astype(bool)
+
+    def projected_columns(self, mask):
+        """Result columns of the projected result as (table, column) pairs:
+        the root's output columns in declared order, then for every further
+        kept table its output columns other than the separator."""
+        ok, m, kept = self.projection(mask)
+        if not ok:
+            raise ValueError("projection not supported")
+        cols = []
+        for t in range(self.n):
+            if not kept[t]:
+                continue
+            for c in range(len(self.q.tables[t])):
+                if (int(m[t]) >> c) & 1 and (t == 0 or c != self.q.sep_col[t]):
+                    cols.append((t, c))
+        return cols
+
+    def projected_result(self, mask):
+        """The projected result by definition: every result tuple restricted to
+        the output attributes (multiplicities kept), sorted by all of them."""
+        cols = self.projected_columns(mask)
+        rows = self.materialize()
+        if not cols:
+            return np.zeros((len(rows), 0), np.int32)
+        vals = np.stack([self.q.tables[t][c][rows[:, t]] for t, c in cols], axis=1).astype(np.int32)
+        order = np.lexsort(vals.T[::-1])
+        return vals[order]
+
+    def projected_table(self, mask, t):
+        m = np.ascontiguousarray(mask, dtype=np.uint32)
+        ok, mn, kept = self.projection(mask)
+        if not ok or not kept[t]:
+            raise ValueError("table is not kept by this projection")
+        k = bin(int(mn[t])).count("1")
+        cap = max(self.q.n_rows(t), 1)
+        keys = np.zeros((cap, max(k, 1)), dtype=np.int32)
+        arrs = [np.zeros(cap, dtype=np.int64) for _ in range(4)]
+        e = lib().orc_projected_table(self.h, _p(m), int(t), _p(keys), *[_p(a) for a in arrs])
+        return dict(keys=keys[:e, :k], c=arrs[0][:e], U=arrs[1][:e], D=arrs[2][:e], F=arrs[3][:e])
