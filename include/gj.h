@@ -214,6 +214,42 @@ void gj_free_colset(gj_colset* cs);
 gj_status gj_desummarize_values(gj_ctx* ctx, const gj_summary* s, const gj_colset* cs, int64_t first_row,
                                 int64_t n_rows, int32_t* out, int64_t* n_written);
 
+/* ---- early projections (Sec. 3.7) ----
+ * Only some attributes are output attributes.  out_cols[t] (host, one word per
+ * table) has bit c set if key column c of table t is one; a join attribute
+ * marked on either table of its edge counts for both.  The projected result is
+ * every join result tuple restricted to the output attributes, each keeping its
+ * multiplicity, sorted by all of them.  Non-output attributes are removed
+ * before the generator is built: a table with no output attribute besides its
+ * separator (the root: none at all) and no kept descendant is deleted -- only
+ * its subtree's completions count, as a frequency carried by its parent's
+ * entries -- and every kept table's entries are grouped by its output columns.
+ * Returns a projected summary (views index the kept tables 0..k-1 in their
+ * original order; gj_summary_n_tables gives k; keys are the output columns in
+ * declared order; c is the projected frequency, an int64 that can exceed any
+ * row count) and the join size in *join_size (host).
+ * Supported when table 0 holds an output attribute and every kept table's
+ * separator is an output attribute; otherwise two kept tables would be linked
+ * through a summed-out attribute and the generator would need a fill-in edge:
+ * GJ_E_GRAPH (root the query at a table that holds output attributes).  No
+ * output attribute, a bit beyond a table's columns, or more than
+ * GJ_MAX_OUT_COLS result columns: GJ_E_INVALID.  A projected summary has no
+ * row ids: gj_desummarize, gj_unroll_gfjs and gj_colset_create reject it. */
+gj_status gj_summarize_projected(gj_ctx* ctx, const gj_factors* f, const uint32_t* out_cols, gj_summary** out,
+                                 int64_t* join_size);
+/* Tables described by a summary (for a projected one, the kept tables). */
+int32_t gj_summary_n_tables(const gj_summary* s);
+/* Rows [first_row, first_row + n_rows) of the sorted result as attribute
+ * values, row-major [n_rows x gj_result_columns(s)] int32: the root's columns
+ * in declared order, then each further table's columns other than its
+ * separator, in table order.  On a projected summary these are the output
+ * attributes; on any other summary every attribute of every result row.  An
+ * entry tuple of the summary is one run of identical rows, so this is
+ * run-length decoding.  `out` is a 16-byte aligned device buffer; *n_written
+ * (host) receives the count; first_row > join size -> GJ_E_RANGE. */
+gj_status gj_desummarize_projected(gj_ctx* ctx, const gj_summary* s, int64_t first_row, int64_t n_rows, int32_t* out,
+                                   int64_t* n_written);
+
 /* ---- weighted join and its adjoint ----
  * Every row r of table t carries a weight w_t[r]; W = sum over result tuples of
  * the product of their rows' weights (W = join size at unit weights).  The

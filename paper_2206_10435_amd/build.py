@@ -28,8 +28,8 @@ FLAGS = [
     "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
-SOURCES = ["factor.hip", "summary.hip", "desum.hip", "desum_values.hip", "weighted.hip", "gfjs.hip", "api.hip",
-           "batch.hip"]
+SOURCES = ["factor.hip", "summary.hip", "desum.hip", "desum_values.hip", "desum_runs.hip", "project.hip",
+           "weighted.hip", "gfjs.hip", "api.hip", "batch.hip"]
 
 
 def _compile(src: str) -> str:

@@ -456,7 +456,7 @@ void launch_summary(const Plan& P, const FPtrs& F, const SPtrs& S, hipStream_t s
   gjk::compact(s, P.d_wl + P.all.off, P.all.n, P.d_tabs + P.all.toff, P.all.tn, P.d_desc, F, S);
 }
 
-static gj_status read_counters(const Plan& P, const FPtrs& F, hipStream_t s, std::vector<int64_t>& out) {
+gj_status read_counters(const Plan& P, const FPtrs& F, hipStream_t s, std::vector<int64_t>& out) {
   out.assign((size_t)P.nt * CNT_STRIDE, 0);
   gj_status st = check(hipMemcpyAsync(out.data(), F.cnt, out.size() * 8, hipMemcpyDeviceToHost, s), "counters");
   if (st) return st;

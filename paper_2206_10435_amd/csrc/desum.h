@@ -30,4 +30,21 @@ struct DesumArgs {
 };
 
 
+// Arguments of the run expansion of a projected summary (desum_runs.hip).
+struct RunTab {
+  const int64_t* cpre;    // surviving entry -> offset of its block inside its group (units of c*U)
+  const int64_t* cc;      // surviving entry -> frequency c (int64)
+  const ChildRec* crec;   // (t >= 1) surviving parent entry -> this table's group
+  int32_t parent;
+};
+
+struct RunArgs {
+  RunTab tab[GJ_MAX_TABLES];
+  int64_t first, n_rows, n_root;
+  int32_t* out;  // row-major [n_rows x n_cols] int32
+  int32_t n_tables, n_cols, tuples_per_lane;
+  int32_t col_tab[GJ_MAX_OUT_COLS];         // table of result column j
+  const int32_t* col_key[GJ_MAX_OUT_COLS];  // its key column, by surviving entry
+};
+
 }  // namespace gjk

@@ -1,0 +1,239 @@
+// Desummarization of a projected summary (Sec. 3.7 early projections, then
+// Sec. 3.6): the result has no row ids, only the output attributes, and every
+// entry tuple (e_0, .., e_{n-1}) of the projected factors is one run of
+// identical value tuples whose length is the product of the entries'
+// frequencies c_t(e_t) (int64: a projected entry stands for whole deleted
+// subtrees).  Writing rows [first, first + n) is therefore run-length
+// decoding: a lane locates its first tuple exactly as the row-id expansion
+// does (one search per table over the block offsets K * pre, here with the
+// wave-cooperative search), then repeats the entry tuple's values until the
+// run ends and steps the entry odometer (the deepest table with a next entry
+// in its group advances; every later table restarts at the first entry of the
+// group under its parent's entry).  Rounds of KS tuples are staged per
+// wavefront in LDS and flushed as 16-byte units.
+#include "desum_kernel.h"
+
+namespace {
+
+template <int N, int NC, int KS>
+__global__ void __launch_bounds__(GJ_BLOCK) k_expand_runs(gjk::RunArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int n = a.n_tables;
+  const int nc = a.n_cols;
+  const int L = a.tuples_per_lane;
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int lb = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int64_t glane = (int64_t)lb * GJ_BLOCK + threadIdx.x;
+  const int64_t my0 = glane * L;
+  const int64_t mycnt = max((int64_t)0, min((int64_t)L, a.n_rows - my0));
+  const int ln = lane_id();
+
+  int32_t e[N], gh[N];
+  uint64_t c[N];
+  int32_t val[NC];
+  uint64_t left = 0;  // tuples left in the current run, the current one included
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    e[t] = 0;
+    gh[t] = 0;
+    c[t] = 1;
+  }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) val[j] = 0;
+
+  if ((glane - ln) * L < a.n_rows) {  // wave-uniform (cooperative search)
+    uint64_t R = (uint64_t)(a.first + min(my0, a.n_rows - 1));
+    uint64_t P = 1;
+    int32_t lo[N];
+    uint64_t mg[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+      lo[t] = 0;
+      mg[t] = 1;
+    }
+    gh[0] = (int32_t)a.n_root;
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+      if (t < n) {
+        const gjk::RunTab& T = a.tab[t];
+        uint64_t Kt = P;
+#pragma unroll
+        for (int j = t + 1; j < N; ++j)
+          if (j < n && a.tab[j].parent < t) Kt *= mg[j];
+        const int32_t x = find_block(T.cpre, lo[t], gh[t], Kt, R, ln);
+        e[t] = x;
+        R -= Kt * (uint64_t)T.cpre[x];
+        c[t] = (uint64_t)T.cc[x];
+        P *= c[t];
+#pragma unroll
+        for (int j = t + 1; j < N; ++j) {
+          if (j < n && a.tab[j].parent == t) {
+            const ChildRec rc = a.tab[j].crec[x];
+            lo[j] = rc.first;
+            gh[j] = rc.end;
+            mg[j] = (uint64_t)rc.M;
+          }
+        }
+      }
+    }
+    left = P - R;  // R: offset inside the run of the entry tuple
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      if (j < nc) {
+        const int tj = a.col_tab[j];
+        int32_t ej = e[0];
+#pragma unroll
+        for (int t = 1; t < N; ++t)
+          if (tj == t) ej = e[t];
+        val[j] = a.col_key[j][ej];
+      }
+    }
+  }
+
+  const int wv = wave_id();
+  int32_t* wlds = reinterpret_cast<int32_t*>(lds_raw) + (int64_t)wv * 64 * KS * nc;
+  const int seg = KS * nc;  // int32 values per lane and round (a multiple of 4)
+  int32_t* my_seg = wlds + (int64_t)ln * seg;
+  const int upl = seg >> 2;  // 16-byte units per lane segment
+  // unit u of lane l's segment is stored at unit u ^ swz(l) when the unit
+  // count is a power of two, so lanes a segment apart use different banks
+  const bool pow2 = (upl & (upl - 1)) == 0;
+  auto swz = [&](int l) -> int { return pow2 ? (((l * upl) >> 3) ^ ((l * upl) >> 4)) & (upl - 1) : 0; };
+  const int my_swz = swz(ln);
+  const int64_t wave_lane0 = glane - ln;
+  const int rounds = (L + KS - 1) / KS;
+  int32_t* out = a.out;
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int64_t done = (int64_t)rd * KS;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        if (j < nc) {
+          const int w = k * nc + j;
+          my_seg[(((w >> 2) ^ my_swz) << 2) + (w & 3)] = val[j];
+        }
+      }
+      if (done + k + 1 < mycnt) {
+        if (--left == 0) {
+          // next entry tuple: the deepest table with a next entry in its group
+          int tc = -1;
+#pragma unroll
+          for (int t = N - 1; t >= 0; --t) {
+            if (t < n && tc < 0) {
+              ++e[t];
+              if (e[t] < gh[t]) tc = t;
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < N; ++t)
+            if (t < n && t == tc) c[t] = (uint64_t)a.tab[t].cc[e[t]];
+          // later tables restart at the first entry of their group
+#pragma unroll
+          for (int t = 1; t < N; ++t) {
+            if (t < n && t > tc) {
+              const int pt = a.tab[t].parent;
+              int32_t ep = 0;
+#pragma unroll
+              for (int i = 0; i < N; ++i)
+                if (i == pt) ep = e[i];
+              const ChildRec rc = a.tab[t].crec[ep];
+              e[t] = rc.first;
+              gh[t] = rc.end;
+              c[t] = (uint64_t)a.tab[t].cc[rc.first];
+            }
+          }
+          left = 1;
+#pragma unroll
+          for (int t = 0; t < N; ++t)
+            if (t < n) left *= c[t];
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            if (j < nc) {
+              const int tj = a.col_tab[j];
+              if (tj >= tc) {
+                int32_t ej = e[0];
+#pragma unroll
+                for (int t = 1; t < N; ++t)
+                  if (tj == t) ej = e[t];
+                val[j] = a.col_key[j][ej];
+              }
+            }
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // flush: lane ln writes 16-byte units of every lane's segment
+    for (int q = ln; q < 64 * upl; q += 64) {
+      const int sl = q / upl;
+      const int u = q - sl * upl;
+      const int64_t tup0 = (wave_lane0 + sl) * L + done;
+      const int64_t scnt = max((int64_t)0, min((int64_t)KS, min((int64_t)L - done, a.n_rows - tup0)));
+      const int64_t words = scnt * nc;
+      const int64_t w0 = (int64_t)u * 4;
+      if (w0 >= words) continue;
+      int32_t* dst = out + tup0 * nc + w0;
+      const int32_t* sp = wlds + (int64_t)sl * seg + ((u ^ swz(sl)) << 2);
+      if (w0 + 4 <= words) {
+        const uint4 v = *reinterpret_cast<const uint4*>(sp);
+        __builtin_nontemporal_store(v.x, reinterpret_cast<uint32_t*>(dst));
+        __builtin_nontemporal_store(v.y, reinterpret_cast<uint32_t*>(dst) + 1);
+        __builtin_nontemporal_store(v.z, reinterpret_cast<uint32_t*>(dst) + 2);
+        __builtin_nontemporal_store(v.w, reinterpret_cast<uint32_t*>(dst) + 3);
+      } else {
+        for (int64_t x = 0; x < words - w0; ++x) dst[x] = sp[x];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+template <int N, int NC>
+void launch_r(hipStream_t s, const gjk::RunArgs& a, int blocks) {
+  constexpr int KS = NC <= 4 ? 8 : 4;
+  const size_t lds = (size_t)GJ_BLOCK * KS * a.n_cols * sizeof(int32_t);
+  hipLaunchKernelGGL((k_expand_runs<N, NC, KS>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a);
+}
+
+template <int N>
+void launch_rn(hipStream_t s, const gjk::RunArgs& a, int blocks) {
+  if (a.n_cols <= 4)
+    launch_r<N, 4>(s, a, blocks);
+  else if (a.n_cols <= 8)
+    launch_r<N, 8>(s, a, blocks);
+  else
+    launch_r<N, GJ_MAX_OUT_COLS>(s, a, blocks);
+}
+
+}  // namespace
+
+namespace gjk {
+
+int expand_runs(hipStream_t s, const RunArgs& a0, int rounds_per_lane) {
+  RunArgs a = a0;
+  if (a.n_rows <= 0) return 0;
+  if (a.n_cols < 1 || a.n_cols > GJ_MAX_OUT_COLS || a.n_tables < 1 || a.n_tables > GJ_MAX_TABLES) return -1;
+  const int ks = a.n_cols <= 4 ? 8 : 4;
+  a.tuples_per_lane = ks * std::max(1, rounds_per_lane);
+  while (a.tuples_per_lane > ks && a.n_rows / a.tuples_per_lane < 256LL * 1024) a.tuples_per_lane /= 2;
+  a.tuples_per_lane = std::max(ks, a.tuples_per_lane / ks * ks);
+  const int64_t lanes = (a.n_rows + a.tuples_per_lane - 1) / a.tuples_per_lane;
+  int64_t blocks = (lanes + GJ_BLOCK - 1) / GJ_BLOCK;
+  blocks = (blocks + 7) / 8 * 8;
+  if (blocks > 0x7fffffff) return -1;
+  if (a.n_tables <= 4)
+    launch_rn<4>(s, a, (int)blocks);
+  else if (a.n_tables <= 8)
+    launch_rn<8>(s, a, (int)blocks);
+  else
+    launch_rn<GJ_MAX_TABLES>(s, a, (int)blocks);
+  return 0;
+}
+
+}  // namespace gjk

@@ -114,6 +114,10 @@ extern "C" gj_status gj_unroll_gfjs(gj_ctx* ctx, const gj_summary* s, int64_t fi
     set_error("gj_unroll_gfjs: bad argument");
     return GJ_E_INVALID;
   }
+  if (s->projected) {
+    set_error("gj_unroll_gfjs: a projected summary has no row ids");
+    return GJ_E_INVALID;
+  }
   if (first_row > s->join_size) {
     set_error("first_row beyond the join size");
     return GJ_E_RANGE;

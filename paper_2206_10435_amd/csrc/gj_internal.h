@@ -82,6 +82,7 @@ struct FPtrs {
   int32_t* mm;
   uint64_t* agg;  // tile aggregates (scratch)
   uint64_t* agg2;
+  int64_t* ecnt;  // projected factors: entry frequencies (null: the row counts)
 };
 
 // Pointers of a plan's summary arrays.

@@ -35,6 +35,22 @@ int desummarize(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables
 // value columns (desum_values.hip): tuples per staging round, and the launch
 int value_round(int n_tables, int n_cols);
 void launch_values(hipStream_t s, const DesumArgs& a, int blocks);
+// run expansion of a projected summary (desum_runs.hip); -1 if it does not fit one launch
+struct RunArgs;
+int expand_runs(hipStream_t s, const RunArgs& a, int rounds_per_lane);
+// projections (project.hip): per kept table of the full factors, the frequency
+// each full entry carries into the projection (its row count times the
+// completions of its deleted children); then per projected entry, the sum
+// over the full entries it groups
+struct ProjArgs {
+  uint32_t kept;                // bit t: table t is kept
+  uint32_t del[GJ_MAX_TABLES];  // bit i: child i of table t is deleted
+  int64_t full_off[GJ_MAX_TABLES];  // projected table -> slot offset of its table in the full plan
+};
+void proj_weights(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F, const SPtrs& S,
+                  const ProjArgs& pa, int64_t* w);
+void proj_counts(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F, const int64_t* w,
+                 const ProjArgs& pa);
 // out[i] = data[perm[i]] for i < n: a row-order column in grouped row order
 void gather_rows(hipStream_t s, const int32_t* perm, const int32_t* data, int64_t n, int32_t* out);
 

@@ -91,6 +91,8 @@ void launch_factors(const Plan& P, const FPtrs& F, hipStream_t s);
 // Summary kernels (asynchronous, capturable).
 void launch_summary(const Plan& P, const FPtrs& F, const SPtrs& S, hipStream_t s);
 gj_status alloc_summary(const Plan& P, Arena& A, SPtrs& S);
+// Host copy of the plan's device counters (synchronizes the stream).
+gj_status read_counters(const Plan& P, const FPtrs& F, hipStream_t s, std::vector<int64_t>& out);
 
 gj_status check(hipError_t e, const char* what);
 

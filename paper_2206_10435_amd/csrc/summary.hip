@@ -23,6 +23,12 @@
 
 namespace {
 
+// Frequency of an entry: its row count, or the given count of a projected
+// factor (where an entry stands for many rows of a deleted subtree).
+__device__ __forceinline__ uint64_t entry_count(const FPtrs& F, int64_t se) {
+  return F.ecnt ? (uint64_t)F.ecnt[se] : (uint64_t)(F.eend[se] - F.estart[se]);
+}
+
 // index of v in the ascending array a[0..n), or -1
 __device__ __forceinline__ int32_t find_sorted(const int32_t* __restrict__ a, int64_t n, int32_t v) {
   int64_t lo = 0, hi = n;
@@ -71,7 +77,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_up_agg(const WorkItem* __restrict_
             U = smul(U, m);
           }
         }
-        const uint64_t c = (uint64_t)(F.eend[se] - F.estart[se]);
+        const uint64_t c = entry_count(F, se);
         cu = smul(c, U);
         S.U[se] = (int64_t)U;
         head = (e == 0 || F.egrp[se] != F.egrp[se - 1]) ? 1u : 0u;
@@ -138,7 +144,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_up_scan(const WorkItem* __restrict
     uint32_t head = 0;
     const bool valid = e < M;
     if (valid) {
-      const uint64_t c = (uint64_t)(F.eend[se] - F.estart[se]);
+      const uint64_t c = entry_count(F, se);
       cu = smul(c, (uint64_t)S.U[se]);
       head = (e == 0 || F.egrp[se] != F.egrp[se - 1]) ? 1u : 0u;
     }
@@ -197,7 +203,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_down(const WorkItem* __restrict__ 
       if (U == 0) continue;
       const uint64_t Dp = d.is_root ? 1ULL : (uint64_t)S.Dg[d.off + F.egrp[se]];
       if (Dp == 0) continue;
-      const uint64_t c = (uint64_t)(F.eend[se] - F.estart[se]);
+      const uint64_t c = entry_count(F, se);
       // c * Dp * product of the other children's messages
       uint64_t term = smul(c, Dp);
       for (int i = 0; i < d.nchild; ++i) {
@@ -228,9 +234,10 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_down(const WorkItem* __restrict__ 
   }
 }
 
-// Survivors per tile: entries with U > 0 and D > 0, groups with M > 0 and D > 0.
+// Survivors per tile: entries with c > 0, U > 0 and D > 0, groups with M > 0
+// and D > 0 (a row count is never 0; a projected frequency can be).
 __device__ __forceinline__ bool entry_survives(const TDesc& d, const FPtrs& F, const SPtrs& S, int64_t se) {
-  if (S.U[se] == 0) return false;
+  if (S.U[se] == 0 || (F.ecnt && F.ecnt[se] == 0)) return false;
   return d.is_root || S.Dg[d.off + F.egrp[se]] > 0;
 }
 __device__ __forceinline__ bool group_survives(const TDesc& d, const SPtrs& S, int64_t sg) {
@@ -283,7 +290,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_compact_write(const WorkItem* __re
       S.e2c[se] = (int32_t)ci;
       if (es) {
         const int64_t sc = d.off + ci;
-        const uint64_t c = (uint64_t)(F.eend[se] - F.estart[se]);
+        const uint64_t c = entry_count(F, se);
         const uint64_t U = (uint64_t)S.U[se];
         const uint64_t Dv = d.is_root ? 1ULL : (uint64_t)S.Dg[d.off + F.egrp[se]];
         for (int k = 0; k < d.k; ++k)

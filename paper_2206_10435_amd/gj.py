@@ -96,6 +96,9 @@ SIGNATURES = {
     "gj_colset_create": (C.c_int, [_vp, _vp, _i32, _vp, _vp, _vp]),
     "gj_free_colset": (None, [_vp]),
     "gj_desummarize_values": (C.c_int, [_vp, _vp, _vp, _i64, _i64, _vp, _vp]),
+    "gj_summarize_projected": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "gj_summary_n_tables": (_i32, [_vp]),
+    "gj_desummarize_projected": (C.c_int, [_vp, _vp, _i64, _i64, _vp, _vp]),
 }
 
 
@@ -206,6 +209,35 @@ class Context:
         q = C.c_int64()
         _check(self.L.gj_summarize(self.h, f.h, C.byref(h), C.byref(q)))
         return Summary(self, h, f.n_tables, int(q.value))
+
+    def summarize_projected(self, f: "Factors", out_cols) -> "Summary":
+        """Early projection: out_cols[t] has bit c set for every output key
+        column c of table t.  The summary's tables are the kept tables."""
+        m = np.ascontiguousarray([int(x) for x in out_cols], dtype=np.uint32)
+        if len(m) != f.n_tables:
+            raise ValueError("one mask word per table")
+        h = C.c_void_p()
+        q = C.c_int64()
+        _check(self.L.gj_summarize_projected(self.h, f.h, m.ctypes.data_as(C.c_void_p), C.byref(h), C.byref(q)))
+        return Summary(self, h, int(self.L.gj_summary_n_tables(h)), int(q.value), projected=True)
+
+    def result_columns(self, s: "Summary") -> int:
+        return int(self.L.gj_result_columns(s.h))
+
+    def desummarize_projected(self, s: "Summary", first_row: int, n_rows: int, out) -> int:
+        """Writes rows [first_row, first_row + n_rows) as attribute values
+        (n_rows x result_columns, row-major int32) into `out`; returns the count."""
+        import torch
+
+        nc = self.result_columns(s)
+        if out.dtype != torch.int32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 device tensor")
+        if out.numel() < n_rows * nc:
+            raise ValueError("out is too small")
+        nw = C.c_int64()
+        _check(self.L.gj_desummarize_projected(self.h, s.h, int(first_row), int(n_rows),
+                                               C.c_void_p(out.data_ptr()), C.byref(nw)))
+        return int(nw.value)
 
     # -- stage 3 ------------------------------------------------------------
     def desummarize(self, s: "Summary", first_row: int, n_rows: int, out) -> int:
@@ -337,8 +369,10 @@ class Factors:
 
 
 class Summary:
-    def __init__(self, ctx: Context, h, n_tables: int, join_size: int, borrowed: bool = False):
+    def __init__(self, ctx: Context, h, n_tables: int, join_size: int, borrowed: bool = False,
+                 projected: bool = False):
         self.ctx, self.h, self.n_tables, self.join_size, self.borrowed = ctx, h, n_tables, join_size, borrowed
+        self.projected = projected
 
     def __del__(self):
         if not self.borrowed and getattr(self, "h", None) is not None and self.ctx.h:
