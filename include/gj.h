@@ -250,6 +250,23 @@ int32_t gj_summary_n_tables(const gj_summary* s);
 gj_status gj_desummarize_projected(gj_ctx* ctx, const gj_summary* s, int64_t first_row, int64_t n_rows, int32_t* out,
                                    int64_t* n_written);
 
+/* ---- storing and reloading a summary (compute-and-store, load-and-desummarize) ----
+ * gj_summary_save writes summary s to the file `path` (host) as its columns
+ * in a fixed binary layout: per table the surviving entries' keys, c, U, D,
+ * F and block offsets, the edge's (s, M, D) and the child records, and, if
+ * with_rows is nonzero, each entry's (count, first position) and the grouped
+ * row ids (a projected summary has none: GJ_E_INVALID).  *bytes_written
+ * (host, may be NULL) receives the file size.  gj_summary_load reads such a
+ * file into a new summary on ctx's device: views, gj_summary_join_size,
+ * gj_result_columns and gj_desummarize_projected work on it, and when it was
+ * saved with rows also gj_desummarize, gj_colset_create and gj_unroll_gfjs,
+ * all with the results of the summary it was saved from.  An unreadable file,
+ * a different version or a malformed header: GJ_E_INVALID.  Free it with
+ * gj_free_summary. */
+gj_status gj_summary_save(gj_ctx* ctx, const gj_summary* s, const char* path, int32_t with_rows,
+                          int64_t* bytes_written);
+gj_status gj_summary_load(gj_ctx* ctx, const char* path, gj_summary** out);
+
 /* ---- weighted join and its adjoint ----
  * Every row r of table t carries a weight w_t[r]; W = sum over result tuples of
  * the product of their rows' weights (W = join size at unit weights).  The

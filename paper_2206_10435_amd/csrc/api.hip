@@ -712,8 +712,9 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
     set_error("gj_desummarize: bad argument");
     return GJ_E_INVALID;
   }
-  if (s->projected) {
-    set_error("gj_desummarize: a projected summary has no row ids (use gj_desummarize_projected)");
+  if (s->projected || !s->f->F.perm) {
+    set_error("gj_desummarize: the summary has no row ids (projected, or loaded without rows): "
+              "use gj_desummarize_projected");
     return GJ_E_INVALID;
   }
   if (first_row > s->join_size) {
@@ -746,8 +747,8 @@ gj_status gj_colset_create(gj_ctx* ctx, const gj_summary* s, int32_t n_cols, con
     set_error("gj_colset_create: bad argument (1 <= n_cols <= %d)", GJ_MAX_OUT_COLS);
     return GJ_E_INVALID;
   }
-  if (s->projected) {
-    set_error("gj_colset_create: a projected summary has no row ids (use gj_desummarize_projected)");
+  if (s->projected || !s->f->F.perm) {
+    set_error("gj_colset_create: the summary has no row ids (projected, or loaded without rows)");
     return GJ_E_INVALID;
   }
   const Plan& P = s->f->plan;

@@ -114,8 +114,8 @@ extern "C" gj_status gj_unroll_gfjs(gj_ctx* ctx, const gj_summary* s, int64_t fi
     set_error("gj_unroll_gfjs: bad argument");
     return GJ_E_INVALID;
   }
-  if (s->projected) {
-    set_error("gj_unroll_gfjs: a projected summary has no row ids");
+  if (s->projected || !s->f->F.perm) {
+    set_error("gj_unroll_gfjs: the summary has no row ids (projected, or loaded without rows)");
     return GJ_E_INVALID;
   }
   if (first_row > s->join_size) {

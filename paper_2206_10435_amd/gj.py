@@ -99,6 +99,8 @@ SIGNATURES = {
     "gj_summarize_projected": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "gj_summary_n_tables": (_i32, [_vp]),
     "gj_desummarize_projected": (C.c_int, [_vp, _vp, _i64, _i64, _vp, _vp]),
+    "gj_summary_save": (C.c_int, [_vp, _vp, C.c_char_p, _i32, _vp]),
+    "gj_summary_load": (C.c_int, [_vp, C.c_char_p, _vp]),
 }
 
 
@@ -220,6 +222,18 @@ class Context:
         q = C.c_int64()
         _check(self.L.gj_summarize_projected(self.h, f.h, m.ctypes.data_as(C.c_void_p), C.byref(h), C.byref(q)))
         return Summary(self, h, int(self.L.gj_summary_n_tables(h)), int(q.value), projected=True)
+
+    def save(self, s: "Summary", path: str, with_rows: bool = True) -> int:
+        """Writes the summary to `path`; returns the file size in bytes."""
+        nb = C.c_int64()
+        _check(self.L.gj_summary_save(self.h, s.h, os.fsencode(path), 1 if with_rows else 0, C.byref(nb)))
+        return int(nb.value)
+
+    def load(self, path: str) -> "Summary":
+        h = C.c_void_p()
+        _check(self.L.gj_summary_load(self.h, os.fsencode(path), C.byref(h)))
+        js = int(self.L.gj_summary_join_size(h))
+        return Summary(self, h, int(self.L.gj_summary_n_tables(h)), js)
 
     def result_columns(self, s: "Summary") -> int:
         return int(self.L.gj_result_columns(s.h))
