@@ -55,7 +55,8 @@ def _traffic(kernel: str, workload: str):
         rec = json.load(open(path))
         import hashlib
 
-        src = open(os.path.join(ROOT, "paper_2206_10435_amd", "csrc", rec["source"]), "rb").read()
+        src = b"".join(open(os.path.join(ROOT, "paper_2206_10435_amd", "csrc", f), "rb").read()
+                       for f in rec["source"].split("+"))
         if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
             return None
         return rec["bytes_per_launch"]
@@ -219,6 +220,135 @@ def batch_leg(ctx, torch, tune: bool):
     }
 
 
+def payload_leg(ctx, torch, q, s, chunk_rows):
+    """Payload gather on the same summary: the two int32 payload columns of
+    every table (8 values, 32 bytes per tuple) materialized through the
+    expansion kernel, beside the row-id output of the same chunks."""
+    from paper_2206_10435_amd import gj  # noqa: F401
+
+    dev = "cuda:0"
+    st = ctx.stream
+    pay = [[torch.from_numpy(c).to(dev) for c in p] for p in q.payload]
+    cols = [(t, pay[t][i]) for t in range(q.n_tables) for i in range(len(pay[t]))]
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    cs = ctx.colset(s, cols)
+    b.record(st)
+    torch.cuda.synchronize()
+    colset_ms = a.elapsed_time(b)
+    nc = len(cols)
+    out = torch.empty(CHUNK * nc, dtype=torch.int32, device=dev)
+    chunks = [c for c in range(len(chunk_rows)) if chunk_rows[c] == CHUNK][:4] or [0]
+    ctx.desummarize_values(s, cs, 0, chunk_rows[0], out)
+    torch.cuda.synchronize()
+    ms = []
+    for c in chunks:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        ctx.desummarize_values(s, cs, c * CHUNK, chunk_rows[c], out)
+        b.record(st)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    avg = float(np.mean(ms))
+    return {
+        "columns": nc,
+        "bytes_per_tuple": nc * 4,
+        "colset_ms": colset_ms,
+        "expand_ms_per_chunk": avg,
+        "tuples_per_s": CHUNK / (avg / 1000.0),
+        "write_GBps": CHUNK * nc * 4 / (avg / 1000.0) / 1e9,
+    }
+
+
+def projection_leg(ctx, torch, tabs, q, Q):
+    """Early projection onto (A, B, C) of the 4-table chain: T3 and T4 are
+    deleted (their completions become T2's frequencies); the projected result
+    is materialized as 3 int32 values per tuple by run expansion."""
+    dev = "cuda:0"
+    st = ctx.stream
+    mask = [3, 2, 0, 0]
+    f = ctx.build_factors(tabs, q.parent, q.sep_col, q.parent_col)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ps = ctx.summarize_projected(f, mask)
+    t1 = time.perf_counter()
+    full = ctx.summarize(f)
+    assert ps.join_size == Q == full.join_size
+    ent_full = sum(int(full.table(t)["c"].shape[0]) for t in range(full.n_tables))
+    ent_proj = sum(int(ps.table(t)["c"].shape[0]) for t in range(ps.n_tables))
+    nc = ctx.result_columns(ps)
+    out = torch.empty(CHUNK * nc, dtype=torch.int32, device=dev)
+    ctx.desummarize_projected(ps, 0, CHUNK, out)
+    torch.cuda.synchronize()
+    ms = []
+    for c in range(4):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        ctx.desummarize_projected(ps, c * CHUNK, CHUNK, out)
+        b.record(st)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    avg = float(np.mean(ms))
+    return {
+        "output_attributes": "A,B,C (tables 3 and 4 deleted)",
+        "summarize_projected_ms": (t1 - t0) * 1000.0,
+        "summary_entries_full": ent_full,
+        "summary_entries_projected": ent_proj,
+        "result_columns": nc,
+        "expand_ms_per_chunk": avg,
+        "tuples_per_s": CHUNK / (avg / 1000.0),
+        "write_GBps": CHUNK * nc * 4 / (avg / 1000.0) / 1e9,
+    }
+
+
+def store_leg(ctx, torch, s, n):
+    """Compute-and-store / load-and-desummarize: the summary written to a file
+    (with and without the grouped row ids), read back, and a chunk expanded
+    from the reloaded summary compared with the original's."""
+    import tempfile
+
+    rec = {}
+    with tempfile.TemporaryDirectory() as d:
+        for rows in (False, True):
+            path = os.path.join(d, f"s{int(rows)}.gjs")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nb = ctx.save(s, path, with_rows=rows)
+            t1 = time.perf_counter()
+            r = ctx.load(path)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            key = "with_rows" if rows else "values_only"
+            rec[key] = {"bytes": nb, "save_ms": (t1 - t0) * 1000.0, "load_ms": (t2 - t1) * 1000.0}
+            if rows:
+                m = 1 << 24
+                a = torch.empty(m * n, dtype=torch.int64, device="cuda:0")
+                b = torch.empty(m * n, dtype=torch.int64, device="cuda:0")
+                ctx.desummarize(s, 7 * m, m, a)
+                ctx.desummarize(r, 7 * m, m, b)
+                rec[key]["reloaded_chunk_identical"] = bool(torch.equal(a, b))
+            del r
+    return rec
+
+
+def fill_ceiling(torch, out):
+    """A plain streaming write of the same buffer (torch's fill), GB/s."""
+    st = torch.cuda.current_stream()
+    out.fill_(1)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        out.fill_(2)
+        b.record(st)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    return out.numel() * out.element_size() / (best / 1000.0) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,7 +359,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tuples", type=int, default=100_000_000)
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
-    ap.add_argument("--extras", action="store_true", help="also time the weighted adjoint and the 256-query batch")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the weighted adjoint, the 256-query batch, payload gather, early projection "
+                         "and storing/reloading the summary")
     ap.add_argument("--calibrate", action="store_true",
                     help="after the timed steps, copy 1 GiB once (a plain copy of known size for counter scaling)")
     args = ap.parse_args()
@@ -312,6 +444,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    fill_gbps = fill_ceiling(torch, out)
     durs = [a.elapsed_time(b) for a, b in exp_ms]
     # full chunks only, for a per-launch figure of the dominant kernel
     full = [d for d, (i) in zip(durs, range(len(durs))) if chunk_rows[i % nchunks] == CHUNK] or durs
@@ -347,6 +480,7 @@ def main():
         "summary_build_rows_per_s": total_rows / build_avg,
         "summary_build_ms": build_avg * 1000.0,
         "expand_kernel_ms": avg_ms,
+        "write_ceiling_GBps": fill_gbps,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -360,6 +494,16 @@ def main():
         rec["tune"] = tune_rec
     if args.extras:
         del out
+        torch.cuda.empty_cache()
+        s = ctx.summarize(ctx.build_factors(tabs, q.parent, q.sep_col, q.parent_col))
+        if q.payload:
+            rec["payload"] = payload_leg(ctx, torch, q, s, chunk_rows)
+            torch.cuda.empty_cache()
+        if args.workload == "chain4":
+            rec["projection"] = projection_leg(ctx, torch, tabs, q, Q)
+            torch.cuda.empty_cache()
+        rec["store"] = store_leg(ctx, torch, s, n)
+        del s
         torch.cuda.empty_cache()
         rec["weighted"] = weighted_leg(ctx, torch)
         rec["batch"] = batch_leg(ctx, torch, args.tune)
