@@ -15,6 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "gj_oracle.cpp")
+SRCS = [SRC, os.path.join(HERE, "gj_natural.cpp")]
 MAXK = 8
 
 OVERFLOW = 3
@@ -24,8 +25,9 @@ NOT_IN_RESULT = 2
 
 def build(force: bool = False) -> str:
     """Compile the oracle with g++ (host only; no HIP headers)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", SRC, "-o", LIB + ".tmp"]
+    stale = not os.path.exists(LIB) or any(os.path.getmtime(LIB) < os.path.getmtime(f) for f in SRCS)
+    if force or stale:
+        cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", *SRCS, "-o", LIB + ".tmp"]
         subprocess.check_call(cmd)
         os.replace(LIB + ".tmp", LIB)
     return LIB
@@ -78,6 +80,13 @@ def lib():
         L.orc_projection.restype = C.c_int
         L.orc_projected_table.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp]
         L.orc_projected_table.restype = i64
+        L.orc_nat_open.restype = vp
+        L.orc_nat_open.argtypes = [i32, vp, vp, vp, vp]
+        L.orc_nat_close.argtypes = [vp]
+        L.orc_nat_materialize.argtypes = [vp, i64, vp]
+        L.orc_nat_materialize.restype = i64
+        L.orc_nat_brute_force.argtypes = [vp, i64, vp]
+        L.orc_nat_brute_force.restype = i64
         _lib = L
     return _lib
 
@@ -281,3 +290,84 @@ class Oracle:
         arrs = [np.zeros(cap, dtype=np.int64) for _ in range(4)]
         e = lib().orc_projected_table(self.h, _p(m), int(t), _p(keys), *[_p(a) for a in arrs])
         return dict(keys=keys[:e, :k], c=arrs[0][:e], U=arrs[1][:e], D=arrs[2][:e], F=arrs[3][:e])
+
+
+class NaturalOracle:
+    """Natural join over named attributes (cyclic queries included): tables is
+    a list of lists of int32 columns, attrs[t][c] the attribute id of column c
+    of table t.  See gj_natural.cpp for the definitions."""
+
+    def __init__(self, tables, attrs):
+        self.tables = [[np.ascontiguousarray(c, dtype=np.int32) for c in tb] for tb in tables]
+        self.attrs = [list(map(int, a)) for a in attrs]
+        n = len(tables)
+        self.n = n
+        self._nrows = np.array([len(tb[0]) if tb else 0 for tb in self.tables], dtype=np.int64)
+        self._nkeys = np.array([len(tb) for tb in self.tables], dtype=np.int32)
+        ptrs = np.zeros(n * MAXK, dtype=np.uint64)
+        at = np.zeros(n * MAXK, dtype=np.int32)
+        for t in range(n):
+            for c, col in enumerate(self.tables[t]):
+                ptrs[t * MAXK + c] = col.ctypes.data
+                at[t * MAXK + c] = self.attrs[t][c]
+        self._ptrs, self._at = ptrs, at
+        self.h = lib().orc_nat_open(n, _p(self._nrows), _p(self._nkeys), _p(ptrs), _p(at))
+
+    def close(self):
+        if self.h:
+            lib().orc_nat_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def join_size(self):
+        return int(lib().orc_nat_materialize(self.h, 2**62, None))
+
+    def materialize(self, limit=None):
+        if limit is None:
+            limit = self.join_size()
+        if limit > 200_000_000:
+            raise MemoryError(f"refusing to materialize {limit} tuples in host memory")
+        out = np.zeros((max(limit, 1), self.n), dtype=np.int32)
+        m = lib().orc_nat_materialize(self.h, int(limit), _p(out))
+        return out[:m]
+
+    def brute_force(self, limit=10**7):
+        out = np.zeros((limit, self.n), dtype=np.int32)
+        m = lib().orc_nat_brute_force(self.h, int(limit), _p(out))
+        return out[:m]
+
+    def attribute_values(self, rows, attr_order):
+        """Values of the given attributes for result rows (row-id tuples)."""
+        where = {}
+        for t in range(self.n):
+            for c, a in enumerate(self.attrs[t]):
+                where.setdefault(a, (t, c))
+        if len(rows) == 0:
+            return np.zeros((0, len(attr_order)), np.int32)
+        return np.stack([self.tables[where[a][0]][where[a][1]][rows[:, where[a][0]]] for a in attr_order],
+                        axis=1).astype(np.int32)
+
+    def sorted_values(self, attr_order, rows=None):
+        """The result as values of attr_order (each tuple keeps its
+        multiplicity), sorted lexicographically in that order."""
+        v = self.attribute_values(self.materialize() if rows is None else rows, attr_order)
+        if v.shape[0] == 0 or v.shape[1] == 0:
+            return v
+        return v[np.lexsort(v.T[::-1])]
+
+    def potential(self, subset, var_order):
+        """Joint potential of the tables in `subset` (the product of their
+        frequency tables, Sec. 3.2.1): the distinct value tuples of their
+        natural join over var_order, ascending, with their counts."""
+        sub = NaturalOracle([self.tables[t] for t in subset], [self.attrs[t] for t in subset])
+        v = sub.sorted_values(var_order)
+        sub.close()
+        if v.shape[0] == 0:
+            return v, np.zeros(0, np.int64)
+        keys, counts = np.unique(v, axis=0, return_counts=True)
+        return keys.astype(np.int32), counts.astype(np.int64)
