@@ -60,6 +60,7 @@ typedef enum {
 #define GJ_MAX_KEYS 8    /* key columns per table */
 #define GJ_MAX_CHILDREN 8
 #define GJ_MAX_OUT_COLS 16 /* value columns per materialized row */
+#define GJ_MAX_ATTRS 64    /* distinct attributes of a natural-join query */
 
 typedef struct gj_ctx gj_ctx;
 typedef struct gj_factors gj_factors;
@@ -266,6 +267,37 @@ gj_status gj_desummarize_projected(gj_ctx* ctx, const gj_summary* s, int64_t fir
 gj_status gj_summary_save(gj_ctx* ctx, const gj_summary* s, const char* path, int32_t with_rows,
                           int64_t* bytes_written);
 gj_status gj_summary_load(gj_ctx* ctx, const char* path, gj_summary** out);
+
+/* ---- cyclic queries: natural joins over named attributes (Sec. 2.2.1, 3.2.1, 3.4) ----
+ * A natural-join query names the attribute of every key column: column c of
+ * table t carries attribute id attr[t * GJ_MAX_KEYS + c] (>= 0), and all
+ * columns with the same id must hold equal values.  Its graph has one node per
+ * attribute and a clique per table; cycles are allowed. */
+typedef struct {
+  int32_t n_tables;      /* 1..GJ_MAX_TABLES */
+  const int32_t* n_keys; /* host [n_tables], 1..GJ_MAX_KEYS each */
+  const int32_t* attr;   /* host [n_tables * GJ_MAX_KEYS] */
+} gj_natural_query;
+
+/* Junction tree of maxcliques (Sec. 2.2.1): min fill-in triangulation of the
+ * attribute graph, its maxcliques, and a maximal spanning tree over separator
+ * sizes (running intersection property).  Attributes are numbered 0..n_attrs-1
+ * by ascending id (attr_id maps back); cliques are attribute bitmasks numbered
+ * in tree order (parent[i] < i, parent[0] = -1; clique 0 holds table 0's
+ * attributes); table t is assigned to the first clique holding all its
+ * attributes.  Host only: no device work.  More than GJ_MAX_ATTRS attributes,
+ * bad counts or negative ids: GJ_E_INVALID; a disconnected query: GJ_E_GRAPH. */
+typedef struct {
+  int32_t n_attrs;
+  int32_t attr_id[GJ_MAX_ATTRS];
+  int32_t elim_order[GJ_MAX_ATTRS]; /* attribute indices in elimination order */
+  int32_t n_fill;                   /* fill-in edges added */
+  int32_t n_cliques;
+  uint64_t clique[GJ_MAX_ATTRS];
+  int32_t parent[GJ_MAX_ATTRS];
+  int32_t table_clique[GJ_MAX_TABLES];
+} gj_junction_tree;
+gj_status gj_junction_tree_build(const gj_natural_query* q, gj_junction_tree* out);
 
 /* ---- weighted join and its adjoint ----
  * Every row r of table t carries a weight w_t[r]; W = sum over result tuples of

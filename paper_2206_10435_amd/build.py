@@ -29,7 +29,8 @@ FLAGS = [
 ]
 
 SOURCES = ["factor.hip", "summary.hip", "desum.hip", "desum_values.hip", "desum_runs.hip", "project.hip",
-           "weighted.hip", "gfjs.hip", "api.hip", "batch.hip", "store.hip"]
+           "weighted.hip", "gfjs.hip", "api.hip", "batch.hip", "store.hip",
+           "jtree.hip"]
 
 
 def _compile(src: str) -> str:

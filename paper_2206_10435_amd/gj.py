@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgj.so")
 GJ_OK, GJ_E_INVALID, GJ_E_GRAPH, GJ_E_OVERFLOW, GJ_E_OOM, GJ_E_DEVICE, GJ_E_RANGE = range(7)
 STATUS_NAMES = {0: "GJ_OK", 1: "GJ_E_INVALID", 2: "GJ_E_GRAPH", 3: "GJ_E_OVERFLOW", 4: "GJ_E_OOM",
                 5: "GJ_E_DEVICE", 6: "GJ_E_RANGE"}
-MAX_TABLES, MAX_KEYS, MAX_CHILDREN = 16, 8, 8
+MAX_TABLES, MAX_KEYS, MAX_CHILDREN, MAX_ATTRS = 16, 8, 8, 64
 
 
 class GJError(RuntimeError):
@@ -51,6 +51,17 @@ class _SummaryView(C.Structure):
 
 class _EdgeView(C.Structure):
     _fields_ = [("n", C.c_int64), ("s", C.c_void_p), ("M", C.c_void_p), ("D", C.c_void_p)]
+
+
+class _NatQuery(C.Structure):
+    _fields_ = [("n_tables", C.c_int32), ("n_keys", C.c_void_p), ("attr", C.c_void_p)]
+
+
+class _JTree(C.Structure):
+    _fields_ = [("n_attrs", C.c_int32), ("attr_id", C.c_int32 * MAX_ATTRS),
+                ("elim_order", C.c_int32 * MAX_ATTRS), ("n_fill", C.c_int32), ("n_cliques", C.c_int32),
+                ("clique", C.c_uint64 * MAX_ATTRS), ("parent", C.c_int32 * MAX_ATTRS),
+                ("table_clique", C.c_int32 * MAX_TABLES)]
 
 
 class Tune(C.Structure):
@@ -101,6 +112,7 @@ SIGNATURES = {
     "gj_desummarize_projected": (C.c_int, [_vp, _vp, _i64, _i64, _vp, _vp]),
     "gj_summary_save": (C.c_int, [_vp, _vp, C.c_char_p, _i32, _vp]),
     "gj_summary_load": (C.c_int, [_vp, C.c_char_p, _vp]),
+    "gj_junction_tree_build": (C.c_int, [_vp, _vp]),
 }
 
 
@@ -142,6 +154,30 @@ def validate(n_rows: Sequence[int], n_keys: Sequence[int], parent, sep_col, pare
         tabs[t] = _Table(int(n), int(k), C.cast(fake, C.c_void_p))
     g, arrs = _graph_struct(parent, sep_col, parent_col)
     _check(L.gj_validate(tabs, C.byref(g)))
+
+
+def _natural_struct(attrs):
+    n = len(attrs)
+    nk = np.array([len(a) for a in attrs], dtype=np.int32)
+    at = np.full(n * MAX_KEYS, -1, dtype=np.int32)
+    for t, a in enumerate(attrs):
+        at[t * MAX_KEYS: t * MAX_KEYS + len(a)] = a
+    return _NatQuery(n, nk.ctypes.data, at.ctypes.data), (nk, at)
+
+
+def junction_tree(attrs) -> dict:
+    """Host-only junction tree of a natural-join query (attrs[t][c] = attribute
+    id of column c of table t): attribute ids, elimination order, fill-in
+    count, maxcliques (as sorted attribute-id lists), parents, table cliques."""
+    L = load_library()
+    q, keep = _natural_struct(attrs)
+    jt = _JTree()
+    _check(L.gj_junction_tree_build(C.byref(q), C.byref(jt)))
+    ids = [jt.attr_id[i] for i in range(jt.n_attrs)]
+    cl = [sorted(ids[i] for i in range(jt.n_attrs) if (jt.clique[c] >> i) & 1) for c in range(jt.n_cliques)]
+    return dict(attr_ids=ids, elim_order=[ids[jt.elim_order[i]] for i in range(jt.n_attrs)],
+                n_fill=int(jt.n_fill), cliques=cl, parent=[int(jt.parent[c]) for c in range(jt.n_cliques)],
+                table_clique=[int(jt.table_clique[t]) for t in range(len(attrs))])
 
 
 class Context:
