@@ -61,6 +61,7 @@ typedef enum {
 #define GJ_MAX_CHILDREN 8
 #define GJ_MAX_OUT_COLS 16 /* value columns per materialized row */
 #define GJ_MAX_ATTRS 64    /* distinct attributes of a natural-join query */
+#define GJ_MAX_CLIQUE_TABLES 8 /* tables joined into one maxclique's potential */
 
 typedef struct gj_ctx gj_ctx;
 typedef struct gj_factors gj_factors;
@@ -298,6 +299,51 @@ typedef struct {
   int32_t table_clique[GJ_MAX_TABLES];
 } gj_junction_tree;
 gj_status gj_junction_tree_build(const gj_natural_query* q, gj_junction_tree* out);
+
+/* POTENTIAL-JOIN (Sec. 3.2.1, Algorithm 1): the joint potential of the
+ * frequency tables of q's tables (1..GJ_MAX_CLIQUE_TABLES; tables[t] holds the
+ * key columns whose attributes q names) over all their attributes -- every
+ * combination of attribute values on which all tables agree, with the product
+ * of the tables' frequencies of their parts.  Variables are the attributes in
+ * ascending id order; entries ascend lexicographically.  Worst-case optimal:
+ * values are bound one variable at a time, extending only prefixes that every
+ * table holding the variable shares.  More than 2^31-1 entries, a table naming
+ * an attribute twice: GJ_E_INVALID / GJ_E_GRAPH.  The view's device pointers
+ * live until gj_free_potential. */
+typedef struct gj_potential gj_potential;
+typedef struct {
+  int64_t n_entries;
+  int32_t n_vars;
+  int32_t attr[GJ_MAX_ATTRS];        /* attribute id of each variable */
+  const int32_t* keys[GJ_MAX_ATTRS]; /* device int32[n_entries] per variable */
+  const int64_t* freq;               /* device int64[n_entries] */
+} gj_potential_view;
+gj_status gj_potential_join(gj_ctx* ctx, const gj_table* tables, const gj_natural_query* q, gj_potential** out);
+gj_status gj_potential_table(const gj_potential* p, gj_potential_view* v);
+void gj_free_potential(gj_potential* p);
+
+/* Summary of a natural-join query, cyclic or not (Sec. 3.4: the same inference
+ * on the junction tree of maxcliques).  tables[t] holds the key columns whose
+ * attributes q names.  The junction tree comes from gj_junction_tree_build; each
+ * maxclique's potential is the POTENTIAL-JOIN of the tables assigned to it (a
+ * clique variable no assigned table holds is restricted by the distinct
+ * projection of a table holding it, which filters without counting); the tree
+ * of clique potentials is summarized like an acyclic query, a separator of
+ * several attributes becoming one column holding the index of the value
+ * combination.  The summary's tables are the cliques (views: keys = the
+ * clique's attributes in ascending id order, then separator index columns;
+ * c = the potential's frequency).  It has no row ids: gj_desummarize_projected
+ * writes the result as values, one column per attribute (the root clique's
+ * attributes, then each further clique's attributes outside its separator;
+ * gj_result_attribute names them), sorted by those columns.  *join_size
+ * (host) receives the join size.  Errors: as gj_junction_tree_build and
+ * gj_potential_join, a clique with more than GJ_MAX_CLIQUE_TABLES tables or
+ * more than GJ_MAX_KEYS columns, more than GJ_MAX_TABLES cliques:
+ * GJ_E_GRAPH; GJ_E_OVERFLOW. */
+gj_status gj_summarize_cyclic(gj_ctx* ctx, const gj_table* tables, const gj_natural_query* q, gj_summary** out,
+                              int64_t* join_size);
+/* Attribute id of result column j of a summary made by gj_summarize_cyclic (-1 otherwise). */
+int32_t gj_result_attribute(const gj_summary* s, int32_t j);
 
 /* ---- weighted join and its adjoint ----
  * Every row r of table t carries a weight w_t[r]; W = sum over result tuples of

@@ -30,7 +30,7 @@ FLAGS = [
 
 SOURCES = ["factor.hip", "summary.hip", "desum.hip", "desum_values.hip", "desum_runs.hip", "project.hip",
            "weighted.hip", "gfjs.hip", "api.hip", "batch.hip", "store.hip",
-           "jtree.hip"]
+           "jtree.hip", "pjoin.hip", "cyclic.hip"]
 
 
 def _compile(src: str) -> str:

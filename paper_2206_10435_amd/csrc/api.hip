@@ -676,6 +676,7 @@ void gj_free_summary(gj_summary* s) {
 
 int32_t gj_result_columns(const gj_summary* s) {
   if (!s) return 0;
+  if (!s->result_cols.empty()) return (int32_t)s->result_cols.size();
   const Plan& P = s->f->plan;
   int32_t L = 0;
   for (int t = P.qfirst[s->query]; t < P.qfirst[s->query + 1]; ++t) L += P.td[t].is_root ? P.td[t].k : P.td[t].k - 1;

@@ -30,6 +30,16 @@ struct DesumArgs {
 };
 
 
+// LDS of an expansion block: every lane stages a round of ks tuples of nc
+// values of wbytes each (whole 16-byte units) in a slot of the next power of
+// two of units.
+inline size_t staging_bytes(int ks, int nc, int wbytes) {
+  const int upl = ks * nc * wbytes / 16;
+  int p = 1;
+  while (p < upl) p <<= 1;
+  return (size_t)GJ_BLOCK * p * 16;
+}
+
 // Arguments of the run expansion of a projected summary (desum_runs.hip).
 struct RunTab {
   const int64_t* cpre;    // surviving entry -> offset of its block inside its group (units of c*U)

@@ -208,17 +208,20 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
   }
 
   const int wv = wave_id();
-  WT* wlds = reinterpret_cast<WT*>(lds_raw) + (int64_t)wv * 64 * KS * nc;
-  // A lane's staged round is one segment of KS*nc values, whole 16-byte units
-  // (the launcher picks KS so).  When the unit count is a power of two, unit
-  // u of lane l's segment is stored at unit u ^ swz(l): without it the lanes
-  // of a write instruction, one segment apart, fall into the same banks.
+  // A lane's staged round is one segment of KS*nc values, upl whole 16-byte
+  // units (the launcher picks KS so), placed in a slot of uplp units, the next
+  // power of two.  Unit u of lane l's segment is stored at unit u ^ swz(l):
+  // without it the lanes of a write instruction, one slot apart, fall into
+  // the same banks.
   const int seg_bytes = KS * nc * (int)sizeof(WT);
   const int upl = seg_bytes >> 4;
-  const bool pow2 = (upl & (upl - 1)) == 0;
-  auto swz = [&](int l) -> int { return pow2 ? (((l * upl) >> 3) ^ ((l * upl) >> 4)) & (upl - 1) : 0; };
+  int uplp = 1;
+  while (uplp < upl) uplp <<= 1;
+  const int slot = uplp << 4;
+  unsigned char* wlds = lds_raw + (int64_t)wv * 64 * slot;
+  auto swz = [&](int l) -> int { return (((l * uplp) >> 3) ^ ((l * uplp) >> 4)) & (uplp - 1); };
   const int my_swz = swz(ln);
-  unsigned char* my_seg = reinterpret_cast<unsigned char*>(wlds) + (int64_t)ln * seg_bytes;
+  unsigned char* my_seg = wlds + (int64_t)ln * slot;
   unsigned char* dst_base = reinterpret_cast<unsigned char*>(a.out);
   const int64_t wave_lane0 = glane - ln;
   const int64_t tup_bytes = (int64_t)nc * (int64_t)sizeof(WT);
@@ -349,25 +352,29 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
       const unsigned char* src = reinterpret_cast<const unsigned char*>(wlds);
       // every lane of the wave staged a whole round (all but the range's end)
       const bool wave_full = (wave_lane0 + 63) * L + done + KS <= a.n_rows;
-      if (pow2 && wave_full) {
-        // unit q = ln + 64 i is unit (ln mod upl) of segment ln / upl + i * 64 / upl
-        // (swz(sl) with sl * upl = sl0 * upl + 64 i, split into its parts)
-        const int lsh = __builtin_ctz(upl);
-        const int u = ln & (upl - 1);
+      if (wave_full) {
+        // slot unit q = ln + 64 i is unit (ln mod uplp) of lane ln / uplp + i * 64 / uplp
+        // (swz(sl) with sl * uplp = sl0 * uplp + 64 i, split into its parts);
+        // units past the segment (u >= upl) are padding and not written
+        const int lsh = __builtin_ctz(uplp);
+        const int u = ln & (uplp - 1);
         const int sl0 = ln >> lsh;
         const int step = 64 >> lsh;
-        const int sa = (sl0 * upl) >> 3, sb = (sl0 * upl) >> 4;
-        const unsigned char* rbase = src + sl0 * seg_bytes;
+        const int sa = (sl0 * uplp) >> 3, sb = (sl0 * uplp) >> 4;
+        const unsigned char* rbase = src + sl0 * slot;
         unsigned char* dst = dst_base + ((wave_lane0 + sl0) * L + done) * tup_bytes + u * 16;
         const int64_t dstep = (int64_t)step * L * tup_bytes;
+        const bool mine = u < upl;
 #pragma unroll
-        for (int i = 0; i < upl; ++i) {
-          const int sw = ((sa + 8 * i) ^ (sb + 4 * i)) & (upl - 1);
-          const uint4 val = *reinterpret_cast<const uint4*>(rbase + i * step * seg_bytes + ((u ^ sw) << 4));
-          __builtin_nontemporal_store(val.x, reinterpret_cast<uint32_t*>(dst));
-          __builtin_nontemporal_store(val.y, reinterpret_cast<uint32_t*>(dst) + 1);
-          __builtin_nontemporal_store(val.z, reinterpret_cast<uint32_t*>(dst) + 2);
-          __builtin_nontemporal_store(val.w, reinterpret_cast<uint32_t*>(dst) + 3);
+        for (int i = 0; i < uplp; ++i) {
+          const int sw = ((sa + 8 * i) ^ (sb + 4 * i)) & (uplp - 1);
+          if (mine) {
+            const uint4 val = *reinterpret_cast<const uint4*>(rbase + i * step * slot + ((u ^ sw) << 4));
+            __builtin_nontemporal_store(val.x, reinterpret_cast<uint32_t*>(dst));
+            __builtin_nontemporal_store(val.y, reinterpret_cast<uint32_t*>(dst) + 1);
+            __builtin_nontemporal_store(val.z, reinterpret_cast<uint32_t*>(dst) + 2);
+            __builtin_nontemporal_store(val.w, reinterpret_cast<uint32_t*>(dst) + 3);
+          }
           dst += dstep;
         }
       } else {
@@ -381,7 +388,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
           const int64_t b0 = (int64_t)u * 16;
           if (b0 >= bytes) continue;
           unsigned char* dst = dst_base + tup0 * tup_bytes + b0;
-          const unsigned char* sp = src + (int64_t)sl * seg_bytes + ((u ^ swz(sl)) << 4);
+          const unsigned char* sp = src + (int64_t)sl * slot + ((u ^ swz(sl)) << 4);
           if (b0 + 16 <= bytes) {
             const uint4 val = *reinterpret_cast<const uint4*>(sp);
             __builtin_nontemporal_store(val.x, reinterpret_cast<uint32_t*>(dst));

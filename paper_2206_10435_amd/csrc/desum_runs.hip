@@ -92,14 +92,16 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_expand_runs(gjk::RunArgs a) {
   }
 
   const int wv = wave_id();
-  int32_t* wlds = reinterpret_cast<int32_t*>(lds_raw) + (int64_t)wv * 64 * KS * nc;
   const int seg = KS * nc;  // int32 values per lane and round (a multiple of 4)
-  int32_t* my_seg = wlds + (int64_t)ln * seg;
   const int upl = seg >> 2;  // 16-byte units per lane segment
-  // unit u of lane l's segment is stored at unit u ^ swz(l) when the unit
-  // count is a power of two, so lanes a segment apart use different banks
-  const bool pow2 = (upl & (upl - 1)) == 0;
-  auto swz = [&](int l) -> int { return pow2 ? (((l * upl) >> 3) ^ ((l * upl) >> 4)) & (upl - 1) : 0; };
+  // a lane's segment sits in a slot of the next power of two of units; unit u
+  // is stored at unit u ^ swz(l), so lanes a slot apart use different banks
+  int uplp = 1;
+  while (uplp < upl) uplp <<= 1;
+  const int slot = uplp << 2;  // int32 values per slot
+  int32_t* wlds = reinterpret_cast<int32_t*>(lds_raw) + (int64_t)wv * 64 * slot;
+  int32_t* my_seg = wlds + (int64_t)ln * slot;
+  auto swz = [&](int l) -> int { return (((l * uplp) >> 3) ^ ((l * uplp) >> 4)) & (uplp - 1); };
   const int my_swz = swz(ln);
   const int64_t wave_lane0 = glane - ln;
   const int rounds = (L + KS - 1) / KS;
@@ -177,7 +179,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_expand_runs(gjk::RunArgs a) {
       const int64_t w0 = (int64_t)u * 4;
       if (w0 >= words) continue;
       int32_t* dst = out + tup0 * nc + w0;
-      const int32_t* sp = wlds + (int64_t)sl * seg + ((u ^ swz(sl)) << 2);
+      const int32_t* sp = wlds + (int64_t)sl * slot + ((u ^ swz(sl)) << 2);
       if (w0 + 4 <= words) {
         const uint4 v = *reinterpret_cast<const uint4*>(sp);
         __builtin_nontemporal_store(v.x, reinterpret_cast<uint32_t*>(dst));
@@ -197,7 +199,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_expand_runs(gjk::RunArgs a) {
 template <int N, int NC>
 void launch_r(hipStream_t s, const gjk::RunArgs& a, int blocks) {
   constexpr int KS = NC <= 4 ? 8 : 4;
-  const size_t lds = (size_t)GJ_BLOCK * KS * a.n_cols * sizeof(int32_t);
+  const size_t lds = gjk::staging_bytes(KS, a.n_cols, (int)sizeof(int32_t));
   hipLaunchKernelGGL((k_expand_runs<N, NC, KS>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a);
 }
 

@@ -15,7 +15,7 @@ template <int N, int NC>
 void launch_val(hipStream_t s, const gjk::DesumArgs& a, int blocks) {
   constexpr int KS = val_ks<N, NC>();
   static_assert(KS * N <= 64, "change mask");
-  const size_t lds = (size_t)GJ_BLOCK * KS * a.n_cols * sizeof(int32_t);
+  const size_t lds = gjk::staging_bytes(KS, a.n_cols, (int)sizeof(int32_t));
   hipLaunchKernelGGL((k_desum<N, NC, int32_t, KS>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a);
 }
 

@@ -91,6 +91,23 @@ void launch_factors(const Plan& P, const FPtrs& F, hipStream_t s);
 // Summary kernels (asynchronous, capturable).
 void launch_summary(const Plan& P, const FPtrs& F, const SPtrs& S, hipStream_t s);
 gj_status alloc_summary(const Plan& P, Arena& A, SPtrs& S);
+// Joint potential of several factors (pjoin.hip): n entries over nv
+// variables, keys SoA with `stride` per variable, ascending, and frequencies.
+struct PotentialOut {
+  int64_t n = 0;
+  int nv = 0;
+  int64_t stride = 1;
+  int32_t* keys = nullptr;
+  int64_t* freq = nullptr;
+};
+// Tables with their bit set in `indicator` only filter: their frequency is
+// counted in another clique's potential.
+gj_status potential_join(gj_ctx* ctx, const gj_factors* f, const std::vector<int>& tabs,
+                         const std::vector<std::vector<int>>& tvar, int nv, Arena& A, PotentialOut& out,
+                         uint32_t indicator = 0);
+// Factors of single-table queries with columns ordered by attribute id (pjoin.hip).
+gj_status sorted_factors(gj_ctx* ctx, int n, const gj_table* tables, const gj_natural_query* q,
+                         std::vector<int32_t>& vars, std::vector<std::vector<int>>& tvar, gj_factors** out);
 // Host copy of the plan's device counters (synchronizes the stream).
 gj_status read_counters(const Plan& P, const FPtrs& F, hipStream_t s, std::vector<int64_t>& out);
 
@@ -118,6 +135,10 @@ struct gj_summary {
   std::vector<int64_t> cnt_host;
   int64_t join_size = 0;
   bool projected = false;  // entries over output attributes only: no row ids
+  // result columns (table, key column) and their attribute ids when they are
+  // not "the root's columns, then every other table's non-separator columns"
+  std::vector<std::pair<int, int>> result_cols;
+  std::vector<int32_t> result_attr;
   explicit gj_summary(gj_ctx* c) : ctx(c), arena(c) {}
 };
 

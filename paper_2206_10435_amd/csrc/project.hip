@@ -281,16 +281,23 @@ gj_status gj_desummarize_projected(gj_ctx* ctx, const gj_summary* s, int64_t fir
     T.cc = s->S.cc + d.off;
     T.crec = d.parent >= 0 ? s->S.crec + d.link_off : nullptr;
     T.parent = d.parent >= 0 ? d.parent - base : -1;
-    for (int c = 0; c < d.k; ++c) {
-      if (!d.is_root && c == d.sep) continue;
-      if (nc == GJ_MAX_OUT_COLS) {
-        set_error("gj_desummarize_projected: more than %d result columns", GJ_MAX_OUT_COLS);
-        return GJ_E_INVALID;
-      }
-      a.col_tab[nc] = t;
-      a.col_key[nc] = s->S.ckey + d.key_off + (int64_t)c * d.n;
-      ++nc;
+  }
+  std::vector<std::pair<int, int>> cols = s->result_cols;
+  if (cols.empty())
+    for (int t = 0; t < n; ++t) {
+      const TDesc& d = P.td[base + t];
+      for (int c = 0; c < d.k; ++c)
+        if (d.is_root || c != d.sep) cols.push_back({t, c});
     }
+  if ((int)cols.size() > GJ_MAX_OUT_COLS) {
+    set_error("gj_desummarize_projected: %d result columns (at most %d)", (int)cols.size(), GJ_MAX_OUT_COLS);
+    return GJ_E_INVALID;
+  }
+  for (auto& tc : cols) {
+    const TDesc& d = P.td[base + tc.first];
+    a.col_tab[nc] = tc.first;
+    a.col_key[nc] = s->S.ckey + d.key_off + (int64_t)tc.second * d.n;
+    ++nc;
   }
   a.first = first_row;
   a.n_rows = nw;

@@ -64,6 +64,11 @@ class _JTree(C.Structure):
                 ("table_clique", C.c_int32 * MAX_TABLES)]
 
 
+class _PotView(C.Structure):
+    _fields_ = [("n_entries", C.c_int64), ("n_vars", C.c_int32), ("attr", C.c_int32 * MAX_ATTRS),
+                ("keys", C.c_void_p * MAX_ATTRS), ("freq", C.c_void_p)]
+
+
 class Tune(C.Structure):
     _fields_ = [("sort_items", C.c_int32), ("radix_bits", C.c_int32), ("desum_rounds", C.c_int32),
                 ("desum_stage", C.c_int32)]
@@ -113,6 +118,11 @@ SIGNATURES = {
     "gj_summary_save": (C.c_int, [_vp, _vp, C.c_char_p, _i32, _vp]),
     "gj_summary_load": (C.c_int, [_vp, C.c_char_p, _vp]),
     "gj_junction_tree_build": (C.c_int, [_vp, _vp]),
+    "gj_potential_join": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "gj_potential_table": (C.c_int, [_vp, _vp]),
+    "gj_free_potential": (None, [_vp]),
+    "gj_summarize_cyclic": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "gj_result_attribute": (_i32, [_vp, _i32]),
 }
 
 
@@ -288,6 +298,39 @@ class Context:
         _check(self.L.gj_desummarize_projected(self.h, s.h, int(first_row), int(n_rows),
                                                C.c_void_p(out.data_ptr()), C.byref(nw)))
         return int(nw.value)
+
+    # -- cyclic queries ------------------------------------------------------
+    def potential_join(self, tables, attrs) -> dict:
+        """Algorithm 1: joint potential of the tables (lists of int32 device
+        columns; attrs[t][c] = attribute id) over all their attributes."""
+        tabs, keep = _tables_struct(tables)
+        q, keep2 = _natural_struct(attrs)
+        h = C.c_void_p()
+        _check(self.L.gj_potential_join(self.h, tabs, C.byref(q), C.byref(h)))
+        try:
+            v = _PotView()
+            _check(self.L.gj_potential_table(h, C.byref(v)))
+            n, nv = int(v.n_entries), int(v.n_vars)
+            keys = (np.stack([self.download(v.keys[i], n, np.int32) for i in range(nv)], axis=1)
+                    if nv else np.zeros((n, 0), np.int32))
+            return dict(attrs=[int(v.attr[i]) for i in range(nv)], keys=keys, freq=self.download(v.freq, n, np.int64))
+        finally:
+            self.L.gj_free_potential(h)
+
+    def summarize_cyclic(self, tables, attrs) -> "Summary":
+        """Summary of a natural-join query over named attributes (cycles
+        allowed): tables are lists of int32 device columns, attrs[t][c] the
+        attribute id of column c of table t.  Expand it with
+        desummarize_projected; result_attributes names its columns."""
+        tabs, keep = _tables_struct(tables)
+        q, keep2 = _natural_struct(attrs)
+        h = C.c_void_p()
+        js = C.c_int64()
+        _check(self.L.gj_summarize_cyclic(self.h, tabs, C.byref(q), C.byref(h), C.byref(js)))
+        return Summary(self, h, int(self.L.gj_summary_n_tables(h)), int(js.value), projected=True)
+
+    def result_attributes(self, s: "Summary"):
+        return [int(self.L.gj_result_attribute(s.h, j)) for j in range(self.result_columns(s))]
 
     # -- stage 3 ------------------------------------------------------------
     def desummarize(self, s: "Summary", first_row: int, n_rows: int, out) -> int:
