@@ -41,6 +41,7 @@ struct PJArgs {
   int32_t n_tabs;
   uint32_t ind;             // bit j: table j only filters (its frequency is counted elsewhere)
   uint32_t has;             // bit j: table j holds the variable being bound
+  int32_t driver;           // >= 0: walk this table's range (the first level's slices)
   int32_t col[PJ_MAX];      // its column in table j
   int64_t n_items;          // frontier items
   const int32_t* lo;        // [n_tabs][cap] ranges of the current frontier
@@ -73,9 +74,9 @@ __device__ __forceinline__ int32_t upper_in(const int32_t* __restrict__ a, int32
 // emit(value, k) for the k-th shared value.  Returns the number of values.
 template <typename F>
 __device__ __forceinline__ int64_t shared_values(const PJArgs& a, int64_t f, F emit) {
-  int d = -1;
+  int d = a.driver;
   int32_t best = 0x7fffffff;
-  for (int j = 0; j < a.n_tabs; ++j) {
+  for (int j = 0; j < a.n_tabs && a.driver < 0; ++j) {
     if (!((a.has >> j) & 1u)) continue;
     const int32_t w = a.hi[j * a.cap + f] - a.lo[j * a.cap + f];
     if (w < best) {
@@ -186,12 +187,25 @@ __global__ void k_scan_add(int64_t* __restrict__ x, int64_t n, const int64_t* __
   }
 }
 
+// The first frontier: `parts` items, item i holding slice i of the driver
+// table's entries (cut where the first variable's value changes, so every
+// value lies in one slice) and every other table's whole range.
 __global__ void k_pj_init(int32_t* lo, int32_t* hi, int n_tabs, const int64_t* __restrict__ cnt,
-                          const int32_t* __restrict__ tidx) {
-  const int j = threadIdx.x;
-  if (j < n_tabs) {
-    lo[j] = 0;
-    hi[j] = (int32_t)cnt[tidx[j] * CNT_STRIDE + CNT_M];
+                          const int32_t* __restrict__ tidx, int driver, const int32_t* __restrict__ dkey,
+                          int64_t parts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= parts) return;
+  const int32_t M = (int32_t)cnt[tidx[driver] * CNT_STRIDE + CNT_M];
+  const int64_t chunk = (M + parts - 1) / parts;
+  auto cut = [&](int64_t p) -> int32_t { return p >= M ? M : lower_in(dkey, 0, M, dkey[p]); };
+  for (int j = 0; j < n_tabs; ++j) {
+    if (j == driver) {
+      lo[j * parts + i] = cut(i * chunk);
+      hi[j * parts + i] = cut((i + 1) * chunk);
+    } else {
+      lo[j * parts + i] = 0;
+      hi[j * parts + i] = (int32_t)cnt[tidx[j] * CNT_STRIDE + CNT_M];
+    }
   }
 }
 
@@ -237,21 +251,37 @@ gj_status potential_join(gj_ctx* ctx, const gj_factors* f, const std::vector<int
       set_error("potential join: variable %d is held by none of the tables", v);
       return GJ_E_GRAPH;
     }
+  // the first variable's driver: the smallest table holding it
+  std::vector<int64_t> cnt;
+  gj_status st = read_counters(P, f->F, s, cnt);
+  if (st) return st;
+  int drv = -1;
+  int64_t drv_m = 0;
+  for (int j = 0; j < k; ++j) {
+    const int64_t M = cnt[tabs[j] * CNT_STRIDE + CNT_M];
+    if (a.tab[j].var[0] == 0 && (drv < 0 || M < drv_m)) {
+      drv = j;
+      drv_m = M;
+    }
+  }
   // frontiers of consecutive levels alternate between two arenas
   Arena tmp(ctx), lvl0(ctx), lvl1(ctx);
   Arena* lvl[2] = {&lvl0, &lvl1};
-  int64_t cap = 1;
-  int32_t* lo = tmp.get_n<int32_t>(k);
-  int32_t* hi = tmp.get_n<int32_t>(k);
+  const int64_t parts = std::max<int64_t>(1, std::min<int64_t>(drv_m / 64, 1 << 16));
+  int64_t cap = parts;
+  int32_t* lo = tmp.get_n<int32_t>(k * parts);
+  int32_t* hi = tmp.get_n<int32_t>(k * parts);
   int32_t* d_tidx = tmp.get_n<int32_t>(k);
   int64_t* d_total = tmp.get_n<int64_t>(1);
   if (!lo || !hi || !d_tidx || !d_total) return GJ_E_OOM;
   std::vector<int32_t> tidx(tabs.begin(), tabs.end());
-  gj_status st = check(hipMemcpyAsync(d_tidx, tidx.data(), k * 4, hipMemcpyHostToDevice, s), "potential join");
-  if (st) return st;
-  hipLaunchKernelGGL(k_pj_init, dim3(1), dim3(64), 0, s, lo, hi, k, f->F.cnt, d_tidx);
-  int64_t n_items = 1;
+  if ((st = check(hipMemcpyAsync(d_tidx, tidx.data(), k * 4, hipMemcpyHostToDevice, s), "potential join")))
+    return st;
+  hipLaunchKernelGGL(k_pj_init, dim3((unsigned)((parts + GJ_BLOCK - 1) / GJ_BLOCK)), dim3(GJ_BLOCK), 0, s, lo, hi, k,
+                     f->F.cnt, d_tidx, drv, a.tab[drv].key[0], parts);
+  int64_t n_items = parts;
   for (int v = 0; v < nv && n_items > 0; ++v) {
+    a.driver = v == 0 ? drv : -1;
     a.has = 0;
     for (int j = 0; j < k; ++j) {
       a.col[j] = -1;

@@ -282,3 +282,17 @@ def random_tree_query(seed: int, n_tables: int, max_rows: int, domain: int, s: f
             cols.append((vals - domain // 3).astype(np.int32))
         tables.append(cols)
     return Query(f"rand{seed}", tables, parent, sep, pcol)
+
+
+def cycle_query(seed: int = BASE_SEED, length: int = 3, n_rows: int = 1_000_000, domain: int = 10_000,
+                s: float = 1.0):
+    """A cyclic natural join T_i(X_i, X_{i+1 mod length}), Zipf(s) keys over
+    [0, domain) with an independent permutation per (table, column): the
+    triangle (length 3) and 4-cycle shapes of cyclic queries.  Returns the
+    tables and their attribute ids."""
+    cfg = 6
+    tables, attrs = [], []
+    for t in range(length):
+        tables.append([zipf_column(seed, cfg, t, c, s, domain, n_rows) for c in range(2)])
+        attrs.append([t, (t + 1) % length])
+    return tables, attrs
