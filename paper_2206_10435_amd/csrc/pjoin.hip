@@ -9,11 +9,14 @@
 // sorted by its variables in the clique's variable order, so the entries that
 // agree with a bound prefix form a contiguous range and, inside it, the next
 // variable's values are sorted.  A frontier item is one bound prefix, held as
-// one entry range per table.  Binding variable v: every item walks the
-// distinct values of v in the smallest range among the tables containing v
-// and keeps a value if each of the other tables holds it too (binary
-// searches); a count pass, an exclusive scan and a write pass emit the child
-// items with the tables' ranges narrowed to that value.  After the last
+// one entry range per table.  Binding variable v: every item's driver is the
+// smallest range among the tables containing v; the driver range is cut into
+// slices of at most PJ_SLICE entries at value boundaries (so a heavy value
+// never serializes one thread and every value lies in one slice); each slice
+// walks its distinct values of v and keeps a value if each of the other tables
+// holds it too (binary searches).  Per level: slice counts, a scan, slice
+// listing, a count pass, a scan and a write pass that emits the child items
+// with the tables' ranges narrowed to the value, in order.  After the last
 // variable every range is one entry; its frequency is the product of the
 // tables' entry counts and its values are read from the entries.
 #include <algorithm>
@@ -27,6 +30,7 @@ using namespace gjh;
 namespace {
 
 constexpr int PJ_MAX = GJ_MAX_CLIQUE_TABLES;
+constexpr int32_t PJ_SLICE = 256;  // driver entries per work unit
 
 struct PJTab {
   const int32_t* key[GJ_MAX_KEYS];  // entry key columns, in clique-variable order
@@ -41,7 +45,6 @@ struct PJArgs {
   int32_t n_tabs;
   uint32_t ind;             // bit j: table j only filters (its frequency is counted elsewhere)
   uint32_t has;             // bit j: table j holds the variable being bound
-  int32_t driver;           // >= 0: walk this table's range (the first level's slices)
   int32_t col[PJ_MAX];      // its column in table j
   int64_t n_items;          // frontier items
   const int32_t* lo;        // [n_tabs][cap] ranges of the current frontier
@@ -70,13 +73,12 @@ __device__ __forceinline__ int32_t upper_in(const int32_t* __restrict__ a, int32
   return l;
 }
 
-// Walks the values shared by every table holding the variable; calls
-// emit(value, k) for the k-th shared value.  Returns the number of values.
-template <typename F>
-__device__ __forceinline__ int64_t shared_values(const PJArgs& a, int64_t f, F emit) {
-  int d = a.driver;
+// Driver of item f: the table with the smallest range among those holding
+// the variable.
+__device__ __forceinline__ int driver_of(const PJArgs& a, int64_t f) {
+  int d = -1;
   int32_t best = 0x7fffffff;
-  for (int j = 0; j < a.n_tabs && a.driver < 0; ++j) {
+  for (int j = 0; j < a.n_tabs; ++j) {
     if (!((a.has >> j) & 1u)) continue;
     const int32_t w = a.hi[j * a.cap + f] - a.lo[j * a.cap + f];
     if (w < best) {
@@ -84,9 +86,41 @@ __device__ __forceinline__ int64_t shared_values(const PJArgs& a, int64_t f, F e
       d = j;
     }
   }
+  return d;
+}
+
+// Slices per item (at least one) and each item's driver.
+__global__ void k_pj_plan(PJArgs a, int32_t* __restrict__ drv, int64_t* __restrict__ nsl) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= a.n_items) return;
+  const int d = driver_of(a, f);
+  drv[f] = d;
+  const int32_t w = a.hi[d * a.cap + f] - a.lo[d * a.cap + f];
+  nsl[f] = w <= 0 ? 1 : (w + PJ_SLICE - 1) / PJ_SLICE;
+}
+
+// Work units: (item, slice) for every slice of every item, in order.
+__global__ void k_pj_units(int64_t n_items, const int64_t* __restrict__ uoff, int64_t n_units,
+                           int32_t* __restrict__ uitem, int32_t* __restrict__ uslice) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n_items) return;
+  const int64_t b = uoff[f], e = f + 1 < n_items ? uoff[f + 1] : n_units;
+  for (int64_t u = b; u < e; ++u) {
+    uitem[u] = (int32_t)f;
+    uslice[u] = (int32_t)(u - b);
+  }
+}
+
+// Walks the values of one work unit shared by every table holding the
+// variable; calls emit(value, k) for the k-th.  Returns the number of values.
+template <typename F>
+__device__ __forceinline__ int64_t shared_values(const PJArgs& a, int64_t f, int d, int32_t slice, F emit) {
   const int32_t* dk = a.tab[d].key[a.col[d]];
-  int32_t p = a.lo[d * a.cap + f];
-  const int32_t ph = a.hi[d * a.cap + f];
+  const int32_t lo = a.lo[d * a.cap + f], hi = a.hi[d * a.cap + f];
+  // slice boundaries moved back to where the value starts
+  auto cut = [&](int64_t p) -> int32_t { return p >= hi ? hi : lower_in(dk, lo, hi, dk[p]); };
+  int32_t p = cut((int64_t)lo + (int64_t)slice * PJ_SLICE);
+  const int32_t ph = cut((int64_t)lo + (int64_t)(slice + 1) * PJ_SLICE);
   int64_t k = 0;
   while (p < ph) {
     const int32_t x = dk[p];
@@ -105,18 +139,24 @@ __device__ __forceinline__ int64_t shared_values(const PJArgs& a, int64_t f, F e
   return k;
 }
 
-__global__ void k_pj_count(PJArgs a, int64_t* __restrict__ cnt) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= a.n_items) return;
-  cnt[f] = shared_values(a, f, [](int32_t, int64_t) {});
+__global__ void k_pj_count(PJArgs a, int64_t n_units, const int32_t* __restrict__ uitem,
+                           const int32_t* __restrict__ uslice, const int32_t* __restrict__ drv,
+                           int64_t* __restrict__ cnt) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n_units) return;
+  const int32_t f = uitem[u];
+  cnt[u] = shared_values(a, f, drv[f], uslice[u], [](int32_t, int64_t) {});
 }
 
-__global__ void k_pj_write(PJArgs a, const int64_t* __restrict__ off, int32_t* __restrict__ nlo,
-                           int32_t* __restrict__ nhi, int64_t ncap) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= a.n_items) return;
-  const int64_t o = off[f];
-  shared_values(a, f, [&](int32_t x, int64_t k) {
+__global__ void k_pj_write(PJArgs a, int64_t n_units, const int32_t* __restrict__ uitem,
+                           const int32_t* __restrict__ uslice, const int32_t* __restrict__ drv,
+                           const int64_t* __restrict__ off, int32_t* __restrict__ nlo, int32_t* __restrict__ nhi,
+                           int64_t ncap) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n_units) return;
+  const int32_t f = uitem[u];
+  const int64_t o = off[u];
+  shared_values(a, f, drv[f], uslice[u], [&](int32_t x, int64_t k) {
     for (int j = 0; j < a.n_tabs; ++j) {
       int32_t l = a.lo[j * a.cap + f], h = a.hi[j * a.cap + f];
       if ((a.has >> j) & 1u) {
@@ -187,25 +227,13 @@ __global__ void k_scan_add(int64_t* __restrict__ x, int64_t n, const int64_t* __
   }
 }
 
-// The first frontier: `parts` items, item i holding slice i of the driver
-// table's entries (cut where the first variable's value changes, so every
-// value lies in one slice) and every other table's whole range.
+// The first frontier: one item holding every table's whole range.
 __global__ void k_pj_init(int32_t* lo, int32_t* hi, int n_tabs, const int64_t* __restrict__ cnt,
-                          const int32_t* __restrict__ tidx, int driver, const int32_t* __restrict__ dkey,
-                          int64_t parts) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= parts) return;
-  const int32_t M = (int32_t)cnt[tidx[driver] * CNT_STRIDE + CNT_M];
-  const int64_t chunk = (M + parts - 1) / parts;
-  auto cut = [&](int64_t p) -> int32_t { return p >= M ? M : lower_in(dkey, 0, M, dkey[p]); };
-  for (int j = 0; j < n_tabs; ++j) {
-    if (j == driver) {
-      lo[j * parts + i] = cut(i * chunk);
-      hi[j * parts + i] = cut((i + 1) * chunk);
-    } else {
-      lo[j * parts + i] = 0;
-      hi[j * parts + i] = (int32_t)cnt[tidx[j] * CNT_STRIDE + CNT_M];
-    }
+                          const int32_t* __restrict__ tidx) {
+  const int j = threadIdx.x;
+  if (j < n_tabs) {
+    lo[j] = 0;
+    hi[j] = (int32_t)cnt[tidx[j] * CNT_STRIDE + CNT_M];
   }
 }
 
@@ -251,37 +279,34 @@ gj_status potential_join(gj_ctx* ctx, const gj_factors* f, const std::vector<int
       set_error("potential join: variable %d is held by none of the tables", v);
       return GJ_E_GRAPH;
     }
-  // the first variable's driver: the smallest table holding it
-  std::vector<int64_t> cnt;
-  gj_status st = read_counters(P, f->F, s, cnt);
-  if (st) return st;
-  int drv = -1;
-  int64_t drv_m = 0;
-  for (int j = 0; j < k; ++j) {
-    const int64_t M = cnt[tabs[j] * CNT_STRIDE + CNT_M];
-    if (a.tab[j].var[0] == 0 && (drv < 0 || M < drv_m)) {
-      drv = j;
-      drv_m = M;
-    }
-  }
   // frontiers of consecutive levels alternate between two arenas
   Arena tmp(ctx), lvl0(ctx), lvl1(ctx);
   Arena* lvl[2] = {&lvl0, &lvl1};
-  const int64_t parts = std::max<int64_t>(1, std::min<int64_t>(drv_m / 64, 1 << 16));
-  int64_t cap = parts;
-  int32_t* lo = tmp.get_n<int32_t>(k * parts);
-  int32_t* hi = tmp.get_n<int32_t>(k * parts);
+  int64_t cap = 1;
+  int32_t* lo = tmp.get_n<int32_t>(k);
+  int32_t* hi = tmp.get_n<int32_t>(k);
   int32_t* d_tidx = tmp.get_n<int32_t>(k);
   int64_t* d_total = tmp.get_n<int64_t>(1);
   if (!lo || !hi || !d_tidx || !d_total) return GJ_E_OOM;
   std::vector<int32_t> tidx(tabs.begin(), tabs.end());
-  if ((st = check(hipMemcpyAsync(d_tidx, tidx.data(), k * 4, hipMemcpyHostToDevice, s), "potential join")))
-    return st;
-  hipLaunchKernelGGL(k_pj_init, dim3((unsigned)((parts + GJ_BLOCK - 1) / GJ_BLOCK)), dim3(GJ_BLOCK), 0, s, lo, hi, k,
-                     f->F.cnt, d_tidx, drv, a.tab[drv].key[0], parts);
-  int64_t n_items = parts;
+  gj_status st = check(hipMemcpyAsync(d_tidx, tidx.data(), k * 4, hipMemcpyHostToDevice, s), "potential join");
+  if (st) return st;
+  hipLaunchKernelGGL(k_pj_init, dim3(1), dim3(64), 0, s, lo, hi, k, f->F.cnt, d_tidx);
+  // exclusive scan of x[0..n) in place; returns the total (synchronizes)
+  auto scan = [&](Arena& L, int64_t* x, int64_t n, int64_t& total) -> gj_status {
+    const int64_t ntiles = (n + GJ_TILE - 1) / GJ_TILE;
+    int64_t* tsum = L.get_n<int64_t>(ntiles);
+    if (!tsum) return GJ_E_OOM;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(GJ_BLOCK), 0, s, x, n, tsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(GJ_BLOCK), 0, s, tsum, ntiles, d_total);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)ntiles), dim3(GJ_BLOCK), 0, s, x, n, tsum);
+    gj_status e = check(hipMemcpyAsync(&total, d_total, 8, hipMemcpyDeviceToHost, s), "potential join");
+    if (!e) e = check(hipStreamSynchronize(s), "potential join");
+    return e;
+  };
+  auto grid = [](int64_t n) { return dim3((unsigned)((n + GJ_BLOCK - 1) / GJ_BLOCK)); };
+  int64_t n_items = 1;
   for (int v = 0; v < nv && n_items > 0; ++v) {
-    a.driver = v == 0 ? drv : -1;
     a.has = 0;
     for (int j = 0; j < k; ++j) {
       a.col[j] = -1;
@@ -297,19 +322,25 @@ gj_status potential_join(gj_ctx* ctx, const gj_factors* f, const std::vector<int
     a.cap = cap;
     Arena& L = *lvl[v & 1];  // held level v-2's frontier, no longer read
     L.release();
-    int64_t* cnt = L.get_n<int64_t>(n_items);
-    const int64_t ntiles = (n_items + GJ_TILE - 1) / GJ_TILE;
-    int64_t* tsum = L.get_n<int64_t>(ntiles);
-    if (!cnt || !tsum) return GJ_E_OOM;
-    const int blocks = (int)((n_items + GJ_BLOCK - 1) / GJ_BLOCK);
-    hipLaunchKernelGGL(k_pj_count, dim3(blocks), dim3(GJ_BLOCK), 0, s, a, cnt);
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(GJ_BLOCK), 0, s, cnt, n_items, tsum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(GJ_BLOCK), 0, s, tsum, ntiles, d_total);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)ntiles), dim3(GJ_BLOCK), 0, s, cnt, n_items, tsum);
+    // work units: slices of every item's driver range
+    int32_t* drv = L.get_n<int32_t>(n_items);
+    int64_t* uoff = L.get_n<int64_t>(n_items);
+    if (!drv || !uoff) return GJ_E_OOM;
+    hipLaunchKernelGGL(k_pj_plan, grid(n_items), dim3(GJ_BLOCK), 0, s, a, drv, uoff);
+    int64_t n_units = 0;
+    if ((st = scan(L, uoff, n_items, n_units))) return st;
+    if (n_units > INT32_MAX) {
+      set_error("potential join: too many work units");
+      return GJ_E_INVALID;
+    }
+    int32_t* uitem = L.get_n<int32_t>(n_units);
+    int32_t* uslice = L.get_n<int32_t>(n_units);
+    int64_t* cnt = L.get_n<int64_t>(n_units);
+    if (!uitem || !uslice || !cnt) return GJ_E_OOM;
+    hipLaunchKernelGGL(k_pj_units, grid(n_items), dim3(GJ_BLOCK), 0, s, n_items, uoff, n_units, uitem, uslice);
+    hipLaunchKernelGGL(k_pj_count, grid(n_units), dim3(GJ_BLOCK), 0, s, a, n_units, uitem, uslice, drv, cnt);
     int64_t total = 0;
-    if ((st = check(hipMemcpyAsync(&total, d_total, 8, hipMemcpyDeviceToHost, s), "potential join")) ||
-        (st = check(hipStreamSynchronize(s), "potential join")))
-      return st;
+    if ((st = scan(L, cnt, n_units, total))) return st;
     if (total > INT32_MAX) {
       set_error("potential join: %lld joint entries (at most 2^31-1)", (long long)total);
       return GJ_E_INVALID;
@@ -318,7 +349,9 @@ gj_status potential_join(gj_ctx* ctx, const gj_factors* f, const std::vector<int
     int32_t* nlo = L.get_n<int32_t>(k * ncap);
     int32_t* nhi = L.get_n<int32_t>(k * ncap);
     if (!nlo || !nhi) return GJ_E_OOM;
-    if (total > 0) hipLaunchKernelGGL(k_pj_write, dim3(blocks), dim3(GJ_BLOCK), 0, s, a, cnt, nlo, nhi, ncap);
+    if (total > 0)
+      hipLaunchKernelGGL(k_pj_write, grid(n_units), dim3(GJ_BLOCK), 0, s, a, n_units, uitem, uslice, drv, cnt, nlo,
+                         nhi, ncap);
     lo = nlo;
     hi = nhi;
     cap = ncap;
