@@ -326,6 +326,24 @@ gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
   }
   P.word_units = std::max<int64_t>(woff, 64);
   P.hist_slots = std::max<int64_t>(hoff, 64);
+  // dense separator indexes: a direct value -> group table where the
+  // separator's value range is at most a few times the table's rows
+  P.didx_slots = 0;
+  for (int t = 0; t < P.nt; ++t) {
+    TDesc& d = P.td[t];
+    d.didx_off = -1;
+    d.drange = 0;
+    d.dmin = 0;
+    if (d.parent < 0 || d.n == 0) continue;
+    const int32_t lo = mm[(t * MAXK + d.sep) * 2], hi = mm[(t * MAXK + d.sep) * 2 + 1];
+    const int64_t range = (int64_t)hi - (int64_t)lo + 1;
+    if (range > 0 && range <= 4 * d.n + 4096 && range <= (1LL << 30)) {
+      d.didx_off = P.didx_slots;
+      d.drange = range;
+      d.dmin = lo;
+      P.didx_slots += range;
+    }
+  }
   // work lists
   P.wl_host.clear();
   P.tabs_host.clear();
@@ -374,11 +392,12 @@ gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
   F.mm = d_mm;
   F.agg = A.get_n<uint64_t>(P.agg_slots);
   F.agg2 = A.get_n<uint64_t>(P.agg_slots);
+  F.didx = A.get_n<int32_t>(P.didx_slots);
   P.d_wl = A.get_n<WorkItem>(std::max<int64_t>((int64_t)P.wl_host.size(), 1));
   P.d_tabs = A.get_n<int32_t>(std::max<int64_t>((int64_t)P.tabs_host.size(), 1));
   P.d_desc = d_desc;
   if (!F.words[0] || !F.words[1] || !F.perm || !F.ekey || !F.estart || !F.eend || !F.egrp || !F.gval || !F.glo ||
-      !F.ghi || !F.cnt || !F.hist || !F.dtot || !F.agg || !F.agg2 || !P.d_wl || !P.d_tabs)
+      !F.ghi || !F.cnt || !F.hist || !F.dtot || !F.agg || !F.agg2 || !F.didx || !P.d_wl || !P.d_tabs)
     return GJ_E_OOM;
   if ((st = check(hipMemcpyAsync(d_desc, P.td.data(), sizeof(TDesc) * P.nt, hipMemcpyHostToDevice, s), "upload")))
     return st;
@@ -407,6 +426,10 @@ void launch_factors(const Plan& P, const FPtrs& F, hipStream_t s) {
     gjk::runs(s, w, P.d_wl + P.allw[w].off, P.allw[w].n, nullptr, 0, P.d_desc, F);
   gjk::runs_scan(s, P.d_tabs + P.all.toff, P.all.tn, P.d_desc, F);
   for (int w = 0; w < 2; ++w) gjk::runs_write(s, w, P.d_wl + P.allw[w].off, P.allw[w].n, P.d_desc, F);
+  if (P.didx_slots > 0) {
+    gjk::fill_i32(s, F.didx, P.didx_slots, -1, -1);
+    gjk::group_index(s, P.d_wl + P.all.off, P.all.n, P.d_desc, F);
+  }
 }
 
 gj_status alloc_summary(const Plan& P, Arena& A, SPtrs& S) {
@@ -427,15 +450,13 @@ gj_status alloc_summary(const Plan& P, Arena& A, SPtrs& S) {
   S.cgval = A.get_n<int32_t>(P.S);
   S.cgM = A.get_n<int64_t>(P.S);
   S.cgD = A.get_n<int64_t>(P.S);
-  S.cglo = A.get_n<int32_t>(P.S);
-  S.cghi = A.get_n<int32_t>(P.S);
-  S.clink = A.get_n<int32_t>(P.link_slots);
   S.ccs = A.get_n<int2>(P.S);
   S.crec = A.get_n<ChildRec>(P.link_slots);
+  S.grec = A.get_n<ChildRec>(P.S);
   S.qsize = A.get_n<int64_t>(P.nq);
   S.qstatus = A.get_n<int32_t>(P.nq);
   void* all[] = {S.U,  S.pre,    S.Mg,    S.Dg,  S.link, S.e2c,  S.g2c,  S.ckey,  S.cc,    S.cU,   S.cD,
-                 S.cF, S.cpre,   S.cstart, S.cgval, S.cgM, S.cgD,  S.cglo, S.cghi, S.clink, S.qsize, S.qstatus, S.ccs, S.crec};
+                 S.cF, S.cpre,   S.cstart, S.cgval, S.cgM, S.cgD,  S.qsize, S.qstatus, S.ccs, S.crec, S.grec};
   for (void* p : all)
     if (!p) return GJ_E_OOM;
   return GJ_OK;

@@ -429,6 +429,22 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_runs_write(const WorkItem* __restr
 
 }  // namespace
 
+// Dense separator index of tables whose separator values span a small range:
+// didx[didx_off + gval(g) - dmin] = g for every separator group g.
+__global__ void __launch_bounds__(GJ_BLOCK) k_group_index(const WorkItem* __restrict__ wl,
+                                                          const TDesc* __restrict__ D, FPtrs F) {
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  if (d.didx_off < 0) return;
+  const int64_t G = F.cnt[w.t * CNT_STRIDE + CNT_G];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t g = base + r * GJ_BLOCK + threadIdx.x;
+    if (g >= G) break;
+    F.didx[d.didx_off + ((int64_t)F.gval[d.off + g] - d.dmin)] = (int32_t)g;
+  }
+}
+
 // One block per table: exclusive scan (in place) of the table's tile
 // aggregates, each a pair of 32-bit counts packed in a uint64 (no carry can
 // cross the halves: counts are < 2^31); the totals go to cnt[t][ca], cnt[t][cb].
@@ -517,6 +533,10 @@ void runs_write(hipStream_t s, int wide, const WorkItem* wl, int nwl, const TDes
     hipLaunchKernelGGL(k_runs_write<1>, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, P.words[0], P.words[1], P.agg, P);
   else
     hipLaunchKernelGGL(k_runs_write<0>, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, P.words[0], P.words[1], P.agg, P);
+}
+
+void group_index(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F) {
+  if (nwl > 0) hipLaunchKernelGGL(k_group_index, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F);
 }
 
 void tile_scan_pair(hipStream_t s, const int32_t* tabs, int ntab, const TDesc* D, uint64_t* agg, int64_t* cnt, int ca,

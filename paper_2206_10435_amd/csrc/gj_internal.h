@@ -59,6 +59,11 @@ struct TDesc {
   int32_t ntiles_sort;      // ceil(n / sort_tile)
   int32_t ntiles;           // ceil(n / GJ_TILE)
   int32_t is_root;
+  // (t >= 1) separator value -> group: didx[didx_off + v - dmin] for v in
+  // [dmin, dmin + drange) when the values are dense enough (didx_off >= 0)
+  int64_t didx_off;
+  int64_t drange;
+  int32_t dmin;
 };
 
 // Rows / entries per tile of the flat kernels (rounds of GJ_BLOCK elements).
@@ -83,6 +88,7 @@ struct FPtrs {
   uint64_t* agg;  // tile aggregates (scratch)
   uint64_t* agg2;
   int64_t* ecnt;  // projected factors: entry frequencies (null: the row counts)
+  int32_t* didx;  // dense separator value -> group indexes (see TDesc)
 };
 
 // Pointers of a plan's summary arrays.
@@ -114,11 +120,9 @@ struct SPtrs {
   int32_t* cgval;
   int64_t* cgM;
   int64_t* cgD;
-  int32_t* cglo;
-  int32_t* cghi;
-  int32_t* clink;
   int2* ccs;  // surviving entry -> (row count, first position in perm)
   ChildRec* crec;  // surviving parent entry -> the child's group (see ChildRec)
+  ChildRec* grec;  // (t >= 1) group of t -> its record (the same for every parent entry)
   int64_t* qsize;
   int32_t* qstatus;
 };

@@ -20,6 +20,9 @@ void runs_write(hipStream_t s, int wide, const WorkItem* wl, int nwl, const TDes
 void tile_scan_pair(hipStream_t s, const int32_t* tabs, int ntab, const TDesc* D, uint64_t* agg, int64_t* cnt, int ca,
                     int cb);
 
+// separator value -> group for tables with a dense index (after the runs)
+void group_index(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F);
+
 // summary.hip
 void fill_i64(hipStream_t s, int64_t* p, int64_t n, int64_t v);
 void up_pass(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,

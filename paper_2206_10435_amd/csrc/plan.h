@@ -62,7 +62,7 @@ struct Plan {
   std::vector<int> qfirst;  // nq + 1
   std::vector<HTable> ht;
   std::vector<TDesc> td;
-  int64_t S = 0, key_slots = 0, link_slots = 0, agg_slots = 0, hist_slots = 0, word_units = 0;
+  int64_t S = 0, key_slots = 0, link_slots = 0, agg_slots = 0, hist_slots = 0, word_units = 0, didx_slots = 0;
   int max_height = 0, max_depth = 0, max_passes = 0;
   // work lists
   std::vector<WorkItem> wl_host;

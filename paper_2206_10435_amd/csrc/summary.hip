@@ -71,7 +71,13 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_up_agg(const WorkItem* __restrict_
             const int ch = d.child[i];
             const TDesc& dc = D[ch];
             const int32_t v = F.ekey[d.key_off + (int64_t)d.child_col[i] * d.n + e];
-            const int32_t j = find_sorted(F.gval + dc.off, F.cnt[ch * CNT_STRIDE + CNT_G], v);
+            int32_t j;
+            if (dc.didx_off >= 0) {
+              const int64_t x = (int64_t)v - dc.dmin;
+              j = (x >= 0 && x < dc.drange) ? F.didx[dc.didx_off + x] : -1;
+            } else {
+              j = find_sorted(F.gval + dc.off, F.cnt[ch * CNT_STRIDE + CNT_G], v);
+            }
             S.link[dc.link_off + e] = j;
             const uint64_t m = j >= 0 ? (uint64_t)S.Mg[dc.off + j] : 0ULL;
             U = smul(U, m);
@@ -204,14 +210,19 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_down(const WorkItem* __restrict__ 
       const uint64_t Dp = d.is_root ? 1ULL : (uint64_t)S.Dg[d.off + F.egrp[se]];
       if (Dp == 0) continue;
       const uint64_t c = entry_count(F, se);
-      // c * Dp * product of the other children's messages
-      uint64_t term = smul(c, Dp);
-      for (int i = 0; i < d.nchild; ++i) {
-        if (i == ci) continue;
-        const TDesc& dc = D[d.child[i]];
-        term = smul(term, (uint64_t)S.Mg[dc.off + S.link[dc.link_off + e]]);
-      }
       const int32_t j = S.link[dt.link_off + e];
+      // c * Dp * product of the other children's messages: U / M_ci when U
+      // is exact (U > 0, so every message is > 0), else the product itself
+      uint64_t term = smul(c, Dp);
+      if (U < SATV) {
+        term = smul(term, U / (uint64_t)S.Mg[dt.off + j]);
+      } else {
+        for (int i = 0; i < d.nchild; ++i) {
+          if (i == ci) continue;
+          const TDesc& dc = D[d.child[i]];
+          term = smul(term, (uint64_t)S.Mg[dc.off + S.link[dc.link_off + e]]);
+        }
+      }
       uint32_t h = ((uint32_t)j * 2654435761u) >> 21;  // 11 bits
       bool placed = false;
 #pragma unroll 1
@@ -316,50 +327,56 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_compact_write(const WorkItem* __re
   }
 }
 
-// Second compaction pass (needs every e2c / g2c): compacted group ranges and
-// the compacted parent-entry -> child-group links.
-__global__ void __launch_bounds__(GJ_BLOCK) k_compact_links(const WorkItem* __restrict__ wl,
-                                                            const TDesc* __restrict__ D, FPtrs F, SPtrs S) {
+// Second compaction pass (needs every e2c / g2c).  What a child's group
+// contributes to its parents' records depends on the group only, so every
+// group's record is built once (k_group_recs) and copied to the records of
+// the surviving parent entries that link to it (k_compact_links).
+__global__ void __launch_bounds__(GJ_BLOCK) k_group_recs(const WorkItem* __restrict__ wl,
+                                                         const TDesc* __restrict__ D, FPtrs F, SPtrs S) {
   const WorkItem w = wl[blockIdx.x];
   const TDesc& d = D[w.t];
+  if (d.is_root) return;
   const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
   const int64_t G = F.cnt[w.t * CNT_STRIDE + CNT_G];
   const int64_t Mc = F.cnt[w.t * CNT_STRIDE + CNT_MC];
   const int64_t base = (int64_t)w.tile * GJ_TILE;
-  if (base >= M) return;
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t g = base + r * GJ_BLOCK + threadIdx.x;
+    if (g >= G) break;
+    const int64_t sg = d.off + g;
+    const int32_t gc = S.g2c[sg];
+    if (gc < 0) continue;  // no surviving parent entry links here
+    const int32_t glo = F.glo[sg], ghi = F.ghi[sg];
+    ChildRec rc;
+    rc.first = glo < M ? S.e2c[d.off + glo] : (int32_t)Mc;
+    rc.end = ghi < M ? S.e2c[d.off + ghi] : (int32_t)Mc;
+    const int2 cs0 = rc.first < rc.end ? S.ccs[d.off + rc.first] : make_int2(0, 0);
+    rc.c0 = cs0.x;
+    rc.st0 = cs0.y;
+    rc.M = S.cgM[d.off + gc];
+    rc.unused = 0;
+    S.grec[sg] = rc;
+  }
+}
+
+__global__ void __launch_bounds__(GJ_BLOCK) k_compact_links(const WorkItem* __restrict__ wl,
+                                                            const TDesc* __restrict__ D, FPtrs F, SPtrs S) {
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  if (d.nchild == 0) return;
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
   for (int r = 0; r < GJ_ROUNDS; ++r) {
     const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
     if (e >= M) break;
     const int64_t se = d.off + e;
-    if (entry_survives(d, F, S, se)) {
-      const int32_t ci = S.e2c[se];
-      for (int i = 0; i < d.nchild; ++i) {
-        const TDesc& dc = D[d.child[i]];
-        const int32_t j = S.link[dc.link_off + e];
-        const int32_t gc = S.g2c[dc.off + j];
-        S.clink[dc.link_off + ci] = gc;
-        // the child's group range in its compacted entries
-        const int64_t Mch = F.cnt[d.child[i] * CNT_STRIDE + CNT_M];
-        const int64_t Mcch = F.cnt[d.child[i] * CNT_STRIDE + CNT_MC];
-        const int32_t glo = F.glo[dc.off + j], ghi = F.ghi[dc.off + j];
-        ChildRec rc;
-        rc.first = glo < Mch ? S.e2c[dc.off + glo] : (int32_t)Mcch;
-        rc.end = ghi < Mch ? S.e2c[dc.off + ghi] : (int32_t)Mcch;
-        const int2 cs0 = rc.first < rc.end ? S.ccs[dc.off + rc.first] : make_int2(0, 0);
-        rc.c0 = cs0.x;
-        rc.st0 = cs0.y;
-        rc.M = gc >= 0 ? S.cgM[dc.off + gc] : 0;
-        rc.unused = 0;
-        S.crec[dc.link_off + ci] = rc;
-      }
-    }
-    if (e < G) {
-      const int32_t gi = S.g2c[se];
-      if (gi >= 0) {
-        const int32_t lo = F.glo[se], hi = F.ghi[se];
-        S.cglo[d.off + gi] = lo < M ? S.e2c[d.off + lo] : (int32_t)Mc;
-        S.cghi[d.off + gi] = hi < M ? S.e2c[d.off + hi] : (int32_t)Mc;
-      }
+    if (!entry_survives(d, F, S, se)) continue;
+    const int32_t ci = S.e2c[se];
+    for (int i = 0; i < d.nchild; ++i) {
+      const TDesc& dc = D[d.child[i]];
+      // a surviving entry's child group survives (its message and its
+      // downward message are both > 0)
+      S.crec[dc.link_off + ci] = S.grec[dc.off + S.link[dc.link_off + e]];
     }
   }
 }
@@ -392,6 +409,7 @@ void compact(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, in
   hipLaunchKernelGGL(k_compact_count, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
   tile_scan_pair(s, tabs, ntab, D, F.agg, F.cnt, CNT_MC, CNT_GC);
   hipLaunchKernelGGL(k_compact_write, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
+  hipLaunchKernelGGL(k_group_recs, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
   hipLaunchKernelGGL(k_compact_links, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
 }
 
