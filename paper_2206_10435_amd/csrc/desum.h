@@ -32,12 +32,13 @@ struct DesumArgs {
 
 // LDS of an expansion block: every lane stages a round of ks tuples of nc
 // values of wbytes each (whole 16-byte units) in a slot of the next power of
-// two of units.
-inline size_t staging_bytes(int ks, int nc, int wbytes) {
+// two of units, or (tight) of exactly its units when that is not a power of
+// two (row-id launches: less LDS per wave, more waves per CU).
+inline size_t staging_bytes(int ks, int nc, int wbytes, bool tight = false) {
   const int upl = ks * nc * wbytes / 16;
   int p = 1;
   while (p < upl) p <<= 1;
-  return (size_t)GJ_BLOCK * p * 16;
+  return (size_t)GJ_BLOCK * (tight ? upl : p) * 16;
 }
 
 // Arguments of the run expansion of a projected summary (desum_runs.hip).

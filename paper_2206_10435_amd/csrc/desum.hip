@@ -6,7 +6,7 @@ namespace {
 template <int N, typename WT>
 void launch_nw(hipStream_t s, const gjk::DesumArgs& a, int ks, int blocks) {
   if (ks == 8 && N * 8 > 64) ks = 4;  // the change mask holds KS * N bits
-  const size_t lds = gjk::staging_bytes(ks, N, (int)sizeof(WT));
+  const size_t lds = gjk::staging_bytes(ks, N, (int)sizeof(WT), true);
   if (ks == 2) {
     hipLaunchKernelGGL((k_desum<N, 0, WT, 2>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a);
   } else if (ks == 8) {

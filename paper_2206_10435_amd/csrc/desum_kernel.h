@@ -212,14 +212,21 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
   // units (the launcher picks KS so), placed in a slot of uplp units, the next
   // power of two.  Unit u of lane l's segment is stored at unit u ^ swz(l):
   // without it the lanes of a write instruction, one slot apart, fall into
-  // the same banks.
+  // the same banks.  Row-id launches whose segment is not a power of two of
+  // units (6 tables of int64 ids: 12 units) use slots of exactly upl units
+  // instead, unswizzled: the padding would cost a quarter of the LDS and with
+  // it occupancy, which bounds expansions of short runs (the general flush
+  // below handles that layout).
   const int seg_bytes = KS * nc * (int)sizeof(WT);
   const int upl = seg_bytes >> 4;
   int uplp = 1;
   while (uplp < upl) uplp <<= 1;
-  const int slot = uplp << 4;
+  const bool tight = NC == 0 && uplp != upl;
+  const int slot = (tight ? upl : uplp) << 4;
   unsigned char* wlds = lds_raw + (int64_t)wv * 64 * slot;
-  auto swz = [&](int l) -> int { return (((l * uplp) >> 3) ^ ((l * uplp) >> 4)) & (uplp - 1); };
+  auto swz = [&](int l) -> int {
+    return tight ? 0 : ((((l * uplp) >> 3) ^ ((l * uplp) >> 4)) & (uplp - 1));
+  };
   const int my_swz = swz(ln);
   unsigned char* my_seg = wlds + (int64_t)ln * slot;
   unsigned char* dst_base = reinterpret_cast<unsigned char*>(a.out);
@@ -352,7 +359,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
       const unsigned char* src = reinterpret_cast<const unsigned char*>(wlds);
       // every lane of the wave staged a whole round (all but the range's end)
       const bool wave_full = (wave_lane0 + 63) * L + done + KS <= a.n_rows;
-      if (wave_full) {
+      if (wave_full && !tight) {
         // slot unit q = ln + 64 i is unit (ln mod uplp) of lane ln / uplp + i * 64 / uplp
         // (swz(sl) with sl * uplp = sl0 * uplp + 64 i, split into its parts);
         // units past the segment (u >= upl) are padding and not written
