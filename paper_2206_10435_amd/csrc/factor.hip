@@ -437,6 +437,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_group_index(const WorkItem* __rest
   const TDesc& d = D[w.t];
   if (d.didx_off < 0) return;
   const int64_t G = F.cnt[w.t * CNT_STRIDE + CNT_G];
+  if (G == d.drange) return;  // every value is a group: the lookup needs no table
   const int64_t base = (int64_t)w.tile * GJ_TILE;
   for (int r = 0; r < GJ_ROUNDS; ++r) {
     const int64_t g = base + r * GJ_BLOCK + threadIdx.x;

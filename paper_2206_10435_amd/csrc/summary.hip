@@ -74,7 +74,10 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_up_agg(const WorkItem* __restrict_
             int32_t j;
             if (dc.didx_off >= 0) {
               const int64_t x = (int64_t)v - dc.dmin;
-              j = (x >= 0 && x < dc.drange) ? F.didx[dc.didx_off + x] : -1;
+              // when every value of the range is a group (a key column such
+              // as a primary key), the group index is the offset itself
+              const bool all = F.cnt[ch * CNT_STRIDE + CNT_G] == dc.drange;
+              j = (x < 0 || x >= dc.drange) ? -1 : all ? (int32_t)x : F.didx[dc.didx_off + x];
             } else {
               j = find_sorted(F.gval + dc.off, F.cnt[ch * CNT_STRIDE + CNT_G], v);
             }
