@@ -368,7 +368,8 @@ void gj_free_wstate(gj_wstate* st);
  * each cover every query (no host synchronization, no allocation inside).
  * tune = NULL uses built-in tile sizes. */
 typedef struct {
-  int32_t sort_items;   /* keys per thread in 64-bit radix-sort tiles (8 or 16) */
+  int32_t sort_items;   /* keys per thread in 64-bit radix-sort tiles (8 or 16;
+                           128-bit tiles always take 8) */
   int32_t radix_bits;   /* digit width of the radix sort (4..8) */
   int32_t desum_rounds; /* staging rounds per lane of the expansion kernel (1..1024) */
   int32_t desum_stage;  /* tuples per lane per LDS staging round: 2, 4 or 8 */

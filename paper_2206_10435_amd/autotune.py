@@ -29,7 +29,7 @@ RADIX_BITS = (6, 7, 8)
 DESUM_STAGE = (2, 4, 8)
 DESUM_ROUNDS = (4, 6, 8, 16, 32)
 
-DEFAULT = dict(sort_items=16, radix_bits=8, desum_rounds=8, desum_stage=4)
+DEFAULT = dict(sort_items=8, radix_bits=8, desum_rounds=8, desum_stage=4)
 
 
 def _cache_path() -> str:
@@ -116,7 +116,7 @@ def tune_factors(ctx, tables, parent, sep_col, parent_col, use_cache: bool = Tru
     return res
 
 
-def tune_desummarize(ctx, summary, out, first_row: int, n_rows: int, sort_items: int = 16, radix_bits: int = 8,
+def tune_desummarize(ctx, summary, out, first_row: int, n_rows: int, sort_items: int = 8, radix_bits: int = 8,
                      use_cache: bool = True) -> dict:
     """Best (desum_stage, desum_rounds) for expanding `n_rows` tuples into `out`."""
     key = signature("desum", [n_rows], f"t{summary.n_tables}|w{out.element_size()}")

@@ -282,7 +282,7 @@ gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
   hipStream_t s = ctx->stream;
   P.radix_bits = ctx->tune.radix_bits;
   P.sort_items[0] = ctx->tune.sort_items == 8 ? 8 : 16;
-  P.sort_items[1] = P.sort_items[0] == 8 ? 4 : 8;
+  P.sort_items[1] = 8;  // 128-bit words: 8 per thread (measured best of 4, 8, 16)
   fill_desc_static(P);
   std::vector<int> all;
   for (int t = 0; t < P.nt; ++t) all.push_back(t);
@@ -509,7 +509,7 @@ gj_status gj_ctx_create(int device, void* hip_stream, gj_alloc_fn alloc, gj_free
   c->alloc = alloc;
   c->free_fn = free_fn;
   c->user = user;
-  c->tune.sort_items = 16;
+  c->tune.sort_items = 8;
   c->tune.radix_bits = 8;
   c->tune.desum_rounds = 8;
   c->tune.desum_stage = 4;

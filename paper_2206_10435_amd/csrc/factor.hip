@@ -509,7 +509,6 @@ void radix_pass(hipStream_t s, int wide, int items, const WorkItem* wl, int nwl,
   }
   GJ_RADIX_CASE(0, 8)
   GJ_RADIX_CASE(0, 16)
-  GJ_RADIX_CASE(1, 4)
   GJ_RADIX_CASE(1, 8)
 #undef GJ_RADIX_CASE
 }
