@@ -384,6 +384,18 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
           }
           dst += dstep;
         }
+      } else if (wave_full) {
+        // unpadded slots: unit q = ln + 64 i is unit q % upl of lane q / upl
+        for (int q = ln; q < 64 * upl; q += 64) {
+          const int sl = q / upl;
+          const int u = q - sl * upl;
+          const uint4 val = *reinterpret_cast<const uint4*>(src + sl * slot + (u << 4));
+          unsigned char* dst = dst_base + ((wave_lane0 + sl) * L + done) * tup_bytes + (u << 4);
+          __builtin_nontemporal_store(val.x, reinterpret_cast<uint32_t*>(dst));
+          __builtin_nontemporal_store(val.y, reinterpret_cast<uint32_t*>(dst) + 1);
+          __builtin_nontemporal_store(val.z, reinterpret_cast<uint32_t*>(dst) + 2);
+          __builtin_nontemporal_store(val.w, reinterpret_cast<uint32_t*>(dst) + 3);
+        }
       } else {
         for (int q = ln; q < 64 * upl; q += 64) {
           const int sl = q / upl;
