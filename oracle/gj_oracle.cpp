@@ -11,7 +11,9 @@
 //     an all-combinations nested loop (brute_force);
 //   * the GFJS of Definition 1 (Sec. 1.2) is "sort the result by all columns,
 //     then run-length encode each column"; sorting is a comparator over the
-//     attribute values, ties broken by the row ids (reading A4 in the design doc);
+//     attribute values, ties broken by the row ids (r_0, .., r_{n-1}), table 0
+//     most significant (the paper orders values only; a join over row
+//     identifiers has to order tuples with equal values somehow);
 //   * the join size is the partition function Z of Eq. 3 (Sec. 2.2): the number
 //     of row combinations that agree on every join edge.  It is counted at the
 //     level of individual rows: down(t,r) = number of ways to complete the
