@@ -17,7 +17,8 @@
 //             the root.  This is the adjoint of the forward pass: one
 //             downward sweep yields the gradient of every weight.
 // Sums over a group run per wavefront (entries of a group are contiguous) and
-// one float64 atomic per run; downward terms are summed per tile in an LDS
+// one float64 atomic per run; an entry's weights are summed the same way over
+// its grouped row positions; downward terms are summed per tile in an LDS
 // hash table first.  At unit weights every value is an integer below 2^53,
 // so every order of summation gives the exact integer counts.
 #include <vector>
@@ -71,20 +72,60 @@ __device__ __forceinline__ double wget(const WPtrs& P, int t, int64_t r) {
   return P.dtype ? reinterpret_cast<const double*>(P.w[t])[r] : (double)reinterpret_cast<const float*>(P.w[t])[r];
 }
 
-// Per entry: summed weights of its rows.
+// The entry whose rows hold grouped position i: the last entry starting at
+// or before i (entries cover the positions in order, the first at 0).
+__device__ __forceinline__ int32_t entry_of_position(const int32_t* __restrict__ estart, int64_t M, int32_t i) {
+  int64_t lo = 0, hi = M;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (estart[mid] <= i)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return (int32_t)lo;
+}
+
+__device__ __forceinline__ double shfl_up_f64(double v, int off) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)b, off);
+  const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(b >> 32), off);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Per entry: summed weights of its rows (cw zeroed beforehand).  One thread
+// per grouped row position, so an entry of many rows (a heavy key) is summed
+// by many threads: each wave adds up its runs of equal entries (positions are
+// in entry order) and the run's last lane adds the run's sum with one atomic.
 __global__ void __launch_bounds__(GJ_BLOCK) k_wcount(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
                                                      FPtrs F, WPtrs P) {
   const WorkItem w = wl[blockIdx.x];
   const TDesc& d = D[w.t];
   const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
   const int64_t base = (int64_t)w.tile * GJ_TILE;
+  const int ln = lane_id();
+  const int64_t wave0 = base + (threadIdx.x - ln);
   for (int r = 0; r < GJ_ROUNDS; ++r) {
-    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
-    if (e >= M) break;
-    const int64_t se = d.off + e;
-    double s = 0.0;
-    for (int32_t i = F.estart[se]; i < F.eend[se]; ++i) s += wget(P, w.t, F.perm[d.off + i]);
-    P.cw[se] = s;
+    if (wave0 + r * GJ_BLOCK >= d.n) break;  // wave-uniform
+    const int64_t i = base + r * GJ_BLOCK + threadIdx.x;
+    int32_t e = -1;
+    double v = 0.0;
+    if (i < d.n) {
+      e = entry_of_position(F.estart + d.off, M, (int32_t)i);
+      v = wget(P, w.t, F.perm[d.off + i]);
+    }
+    const int32_t eprev = __shfl_up(e, 1);
+    const bool head = ln == 0 || eprev != e;
+    const uint64_t heads = __ballot(head);
+    const int sst = 63 - __clzll(heads & (ln == 63 ? ~0ull : ((2ull << ln) - 1)));
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double u = shfl_up_f64(v, off);
+      if (ln - off >= sst) v += u;
+    }
+    const int32_t enext = __shfl_down(e, 1);
+    const bool tail = ln == 63 || enext != e;
+    if (tail && e >= 0) atomicAdd(&P.cw[d.off + e], v);
   }
 }
 
@@ -200,6 +241,8 @@ struct GPtrs {
   void* g[GJ_MAX_TABLES];
 };
 
+// One thread per grouped row position (an entry of many rows is spread over
+// many threads).
 __global__ void __launch_bounds__(GJ_BLOCK) k_wgrad(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
                                                     FPtrs F, WPtrs P, const double* __restrict__ gW, GPtrs grad) {
   const WorkItem w = wl[blockIdx.x];
@@ -207,20 +250,18 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_wgrad(const WorkItem* __restrict__
   const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
   const int64_t base = (int64_t)w.tile * GJ_TILE;
   const double g0 = *gW;
+  void* gp = grad.g[w.t];
   for (int r = 0; r < GJ_ROUNDS; ++r) {
-    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
-    if (e >= M) break;
-    const int64_t se = d.off + e;
+    const int64_t i = base + r * GJ_BLOCK + threadIdx.x;
+    if (i >= d.n) break;
+    const int64_t se = d.off + entry_of_position(F.estart + d.off, M, (int32_t)i);
     const double Dv = d.is_root ? 1.0 : P.Dw[d.off + F.egrp[se]];
     const double gv = g0 * P.Uw[se] * Dv;
-    void* gp = grad.g[w.t];
-    for (int32_t i = F.estart[se]; i < F.eend[se]; ++i) {
-      const int32_t row = F.perm[d.off + i];
-      if (P.dtype)
-        reinterpret_cast<double*>(gp)[row] = gv;
-      else
-        reinterpret_cast<float*>(gp)[row] = (float)gv;
-    }
+    const int32_t row = F.perm[d.off + i];
+    if (P.dtype)
+      reinterpret_cast<double*>(gp)[row] = gv;
+    else
+      reinterpret_cast<float*>(gp)[row] = (float)gv;
   }
 }
 
@@ -289,6 +330,7 @@ gj_status gj_weighted_forward(gj_ctx* ctx, const gj_factors* fc, const void* con
   const WPtrs P = wptrs(st);
   fill_f64(s, st->Mw, Pl.S, 0.0);
   fill_f64(s, st->W, 1, 0.0);
+  fill_f64(s, st->cw, Pl.S, 0.0);
   hipLaunchKernelGGL(k_wcount, dim3(std::max(1, Pl.all.n)), dim3(GJ_BLOCK), 0, s, Pl.d_wl + Pl.all.off, Pl.d_desc,
                      f->F, P);
   for (int h = 0; h <= Pl.max_height; ++h) {
