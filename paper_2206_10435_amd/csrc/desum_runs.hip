@@ -10,7 +10,8 @@
 // run ends and steps the entry odometer (the deepest table with a next entry
 // in its group advances; every later table restarts at the first entry of the
 // group under its parent's entry).  Rounds of KS tuples are staged per
-// wavefront in LDS and flushed as 16-byte units.
+// wavefront in LDS and flushed as 16-byte units; a wave inside a single run
+// skips all of that and fills its range.
 #include "desum_kernel.h"
 
 namespace {
@@ -88,6 +89,54 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_expand_runs(gjk::RunArgs a) {
           if (tj == t) ej = e[t];
         val[j] = a.col_key[j][ej];
       }
+    }
+  }
+
+  // A wave whose whole range lies inside one run (the usual case when runs
+  // are long, as for a projection's products of frequencies) writes one value
+  // tuple repeated: a coalesced fill of 16-byte units, with no staging.  Lane
+  // 0's run covers the wave's range when its remaining length reaches the
+  // range's end; every lane then holds the same values.
+  {
+    const int64_t wbase = (glane - ln) * L;  // first tuple of the wave
+    const int64_t wspan = 64LL * L;
+    bool one_run = false;
+    if (wbase < a.n_rows && wbase + wspan <= a.n_rows) {
+      const uint32_t l_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)left);
+      const uint32_t l_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(left >> 32));
+      one_run = (((uint64_t)l_hi << 32) | l_lo) >= (uint64_t)wspan;
+    }
+    if (one_run) {
+      // int32 index x of the wave's region holds column x mod nc; the region
+      // starts at a tuple boundary and spans 64 L nc values (whole units)
+      uint4* dst = reinterpret_cast<uint4*>(a.out + wbase * nc);
+      const int units = L * nc / 4;  // per lane
+      int ph = (4 * ln) % nc;        // column of the lane's first value
+      const int step = 256 % nc;     // 64 units further on
+      auto pick = [&](int col) -> int32_t {
+        int32_t x = val[0];
+#pragma unroll
+        for (int j = 1; j < NC; ++j)
+          if (j == col) x = val[j];
+        return x;
+      };
+      for (int i = 0; i < units; ++i) {
+        int c1 = ph + 1, c2 = ph + 2, c3 = ph + 3;
+        c1 -= c1 >= nc ? nc : 0;
+        c2 -= c2 >= nc ? nc : 0;
+        c2 -= c2 >= nc ? nc : 0;
+        c3 -= c3 >= nc ? nc : 0;
+        c3 -= c3 >= nc ? nc : 0;
+        c3 -= c3 >= nc ? nc : 0;
+        uint4* d = dst + ln + 64 * i;
+        __builtin_nontemporal_store((uint32_t)pick(ph), reinterpret_cast<uint32_t*>(d));
+        __builtin_nontemporal_store((uint32_t)pick(c1), reinterpret_cast<uint32_t*>(d) + 1);
+        __builtin_nontemporal_store((uint32_t)pick(c2), reinterpret_cast<uint32_t*>(d) + 2);
+        __builtin_nontemporal_store((uint32_t)pick(c3), reinterpret_cast<uint32_t*>(d) + 3);
+        ph += step;
+        ph -= ph >= nc ? nc : 0;
+      }
+      return;
     }
   }
 

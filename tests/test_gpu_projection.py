@@ -113,6 +113,18 @@ def test_cfg1_chain3(gctx, oracle_mod):
         _check(gctx, oracle_mod, q, mask, windows=(mask == [3, 2, 0]))
 
 
+@pytest.mark.parametrize("n,rows,mask", [(2, 3000, [1, 0]), (2, 3000, [3, 0]), (2, 3000, [3, 2]),
+                                         (3, 300, [3, 2, 2]), (4, 80, [3, 2, 2, 2])],
+                         ids=["A", "AB", "ABC", "ABCD", "ABCDE"])
+def test_long_runs(gctx, oracle_mod, n, rows, mask):
+    """Chains over two key values: the projected result is a handful of runs
+    of 1e5 to 1e6 identical tuples, so whole waves of the run expansion lie
+    inside one run (1 to 5 columns per tuple), whole and from unaligned
+    offsets."""
+    q = W.chain_query(31, 9, n, rows, 2, 0.0, name=f"long_runs{n}")
+    _check(gctx, oracle_mod, q, mask)
+
+
 def test_values_of_unprojected_summary(gctx, oracle_mod):
     """On a full summary, run expansion writes every attribute of every result
     row: the oracle's sorted result mapped to its values."""
