@@ -27,12 +27,23 @@ using namespace gjh;
 
 namespace {
 
-// row -> index of its entry, for every entry of a one-table factor
-__global__ void k_entry_ids(const int32_t* __restrict__ estart, const int32_t* __restrict__ eend,
-                            const int32_t* __restrict__ perm, const int64_t* __restrict__ cnt, int32_t* __restrict__ id) {
+// row -> index of its entry, for every entry of a one-table factor: one
+// thread per grouped position (an entry of many rows is spread over many
+// threads); the entry of position x is the last one starting at or before x
+__global__ void k_entry_ids(const int32_t* __restrict__ estart, int64_t n, const int32_t* __restrict__ perm,
+                            const int64_t* __restrict__ cnt, int32_t* __restrict__ id) {
   const int64_t M = cnt[CNT_M];
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M; e += (int64_t)gridDim.x * blockDim.x)
-    for (int32_t x = estart[e]; x < eend[e]; ++x) id[perm[x]] = (int32_t)e;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = M;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (estart[mid] <= x)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    id[perm[x]] = (int32_t)lo;
+  }
 }
 
 int popc(uint64_t x) { return __builtin_popcountll(x); }
@@ -199,8 +210,7 @@ gj_status gj_summarize_cyclic(gj_ctx* ctx, const gj_table* tables, const gj_natu
     const TDesc& d = g->plan.td[0];
     if (tot > 0)
       hipLaunchKernelGGL(k_entry_ids, dim3((unsigned)std::min<int64_t>((tot + GJ_BLOCK - 1) / GJ_BLOCK, 4096)),
-                         dim3(GJ_BLOCK), 0, hs, g->F.estart + d.off, g->F.eend + d.off, g->F.perm + d.off, g->F.cnt,
-                         id);
+                         dim3(GJ_BLOCK), 0, hs, g->F.estart + d.off, tot, g->F.perm + d.off, g->F.cnt, id);
     st = check(hipStreamSynchronize(hs), "separator ids");
     gj_free_factors(g);
     if (st) return st;

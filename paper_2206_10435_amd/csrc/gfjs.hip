@@ -22,11 +22,24 @@ namespace {
 
 constexpr int TILE = GJ_TILE;
 
-__global__ void k_rmap(const int32_t* __restrict__ perm, const int2* __restrict__ ccs, int64_t nent,
+// row -> surviving entry: one thread per grouped position p (an entry of many
+// rows is spread over many threads); its entry is the last surviving one
+// starting at or before p, if p lies inside it (rows of pruned entries are
+// never looked up)
+__global__ void k_rmap(const int32_t* __restrict__ perm, const int2* __restrict__ ccs, int64_t nent, int64_t n,
                        int32_t* __restrict__ rmap) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nent; e += (int64_t)gridDim.x * blockDim.x) {
-    const int2 cs = ccs[e];
-    for (int32_t i = 0; i < cs.x; ++i) rmap[perm[cs.y + i]] = (int32_t)e;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    if (ccs[0].y > p) continue;
+    int64_t lo = 0, hi = nent;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (ccs[mid].y <= p)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int2 cs = ccs[lo];
+    if (p < (int64_t)cs.y + cs.x) rmap[perm[p]] = (int32_t)lo;
   }
 }
 
@@ -161,8 +174,8 @@ extern "C" gj_status gj_unroll_gfjs(gj_ctx* ctx, const gj_summary* s, int64_t fi
     const TDesc& d = P.td[base + t];
     const int64_t nent = s->cnt_host[(base + t) * CNT_STRIDE + CNT_MC];
     if (nent > 0)
-      hipLaunchKernelGGL(k_rmap, dim3((unsigned)std::min<int64_t>((nent + 255) / 256, 4096)), dim3(256), 0, st,
-                         s->f->F.perm + d.off, s->S.ccs + d.off, nent, rmap + roff[t]);
+      hipLaunchKernelGGL(k_rmap, dim3((unsigned)std::min<int64_t>((d.n + 255) / 256, 4096)), dim3(256), 0, st,
+                         s->f->F.perm + d.off, s->S.ccs + d.off, nent, d.n, rmap + roff[t]);
   }
   if ((r = check(hipMemsetAsync(flags, 0, rows, st), "gfjs flags"))) return r;
   for (size_t i = 0; i < cols.size(); ++i) {
