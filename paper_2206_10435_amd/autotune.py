@@ -27,9 +27,9 @@ from typing import Dict, List, Optional, Sequence
 SORT_ITEMS = (8, 16)
 RADIX_BITS = (6, 7, 8)
 DESUM_STAGE = (2, 4, 8)
-DESUM_ROUNDS = (4, 6, 8, 16, 32)
+DESUM_ROUNDS = (0, 4, 6, 8, 16, 32)  # 0: about 640 bytes per lane
 
-DEFAULT = dict(sort_items=8, radix_bits=8, desum_rounds=8, desum_stage=4)
+DEFAULT = dict(sort_items=8, radix_bits=8, desum_rounds=0, desum_stage=4)
 
 
 def _cache_path() -> str:

@@ -233,7 +233,7 @@ class Context:
             self.L.gj_ctx_destroy(self.h)
             self.h = None
 
-    def set_tune(self, sort_items=8, radix_bits=8, desum_rounds=8, desum_stage=4):
+    def set_tune(self, sort_items=8, radix_bits=8, desum_rounds=0, desum_stage=4):
         t = Tune(sort_items, radix_bits, desum_rounds, desum_stage)
         _check(self.L.gj_ctx_set_tune(self.h, C.byref(t)))
 
