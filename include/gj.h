@@ -372,7 +372,8 @@ typedef struct {
                            128-bit tiles always take 8) */
   int32_t radix_bits;   /* digit width of the radix sort (4..8) */
   int32_t desum_rounds; /* staging rounds per lane of the expansion kernel (1..1024),
-                           or 0: as many as make about 640 bytes of output per lane */
+                           or 0: as many as make about 640 bytes of output per lane
+                           and at least 16 tuples */
   int32_t desum_stage;  /* tuples per lane per LDS staging round: 2, 4 or 8 */
 } gj_tune;
 gj_status gj_batch_create(gj_ctx* ctx, int32_t n_queries, const int32_t* q_off, const gj_table* tables,

@@ -52,10 +52,11 @@ int desummarize(hipStream_t s, const DesumArgs& a0, int rowid_bytes, int n_table
   if (n_tables > GJ_MAX_TABLES) return -1;
   a.n_tables = n_tables;
   a.k_round = ks;
-  // rounds_per_lane 0: about 640 bytes of output per lane (measured best for
-  // 32- and 48-byte tuples, row ids or values)
+  // rounds_per_lane 0: about 640 bytes of output per lane, at least 16 tuples
+  // (measured best for tuples of 12 to 64 bytes, row ids or values)
   const int tup_bytes = values ? a0.n_cols * 4 : n_tables * rowid_bytes;
-  a.tuples_per_lane = rounds_per_lane > 0 ? rs * rounds_per_lane : std::max(rs, 640 / tup_bytes / rs * rs);
+  a.tuples_per_lane = rounds_per_lane > 0 ? rs * rounds_per_lane
+                                          : std::max(rs, std::max(16, 640 / tup_bytes) / rs * rs);
   // a smaller per-lane range when the chunk would not fill the chip
   while (a.tuples_per_lane > rs && a.n_rows / a.tuples_per_lane < 256LL * 1024) a.tuples_per_lane /= 2;
   a.tuples_per_lane = std::max(rs, a.tuples_per_lane / rs * rs);

@@ -271,8 +271,9 @@ int expand_runs(hipStream_t s, const RunArgs& a0, int rounds_per_lane) {
   if (a.n_rows <= 0) return 0;
   if (a.n_cols < 1 || a.n_cols > GJ_MAX_OUT_COLS || a.n_tables < 1 || a.n_tables > GJ_MAX_TABLES) return -1;
   const int ks = a.n_cols <= 4 ? 8 : 4;
-  // rounds_per_lane 0: about 640 bytes of output per lane
-  a.tuples_per_lane = rounds_per_lane > 0 ? ks * rounds_per_lane : std::max(ks, 640 / (a.n_cols * 4) / ks * ks);
+  // rounds_per_lane 0: about 640 bytes of output per lane, at least 16 tuples
+  a.tuples_per_lane =
+      rounds_per_lane > 0 ? ks * rounds_per_lane : std::max(ks, std::max(16, 640 / (a.n_cols * 4)) / ks * ks);
   while (a.tuples_per_lane > ks && a.n_rows / a.tuples_per_lane < 256LL * 1024) a.tuples_per_lane /= 2;
   a.tuples_per_lane = std::max(ks, a.tuples_per_lane / ks * ks);
   const int64_t lanes = (a.n_rows + a.tuples_per_lane - 1) / a.tuples_per_lane;
