@@ -257,7 +257,7 @@ gj_status gj_summarize_cyclic(gj_ctx* ctx, const gj_table* tables, const gj_natu
   const Plan& PP = pf->plan;
   gjk::ProjArgs pa{};
   for (int i = 0; i < k; ++i) pa.full_off[i] = woff[i];
-  gjk::proj_counts(hs, PP.d_wl + PP.all.off, PP.all.n, PP.d_desc, pf->F, w, pa);
+  gjk::proj_counts(hs, PP.d_wl + PP.all.off, PP.all.n, PP.d_desc, pf->F, w, pa, PP.S);
 
   gj_summary* s = new gj_summary(ctx);
   s->f = pf;

@@ -52,8 +52,9 @@ struct ProjArgs {
 };
 void proj_weights(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F, const SPtrs& S,
                   const ProjArgs& pa, int64_t* w);
+// (zeroes F.ecnt's `slots` first)
 void proj_counts(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F, const int64_t* w,
-                 const ProjArgs& pa);
+                 const ProjArgs& pa, int64_t slots);
 // out[i] = data[perm[i]] for i < n: a row-order column in grouped row order
 void gather_rows(hipStream_t s, const int32_t* perm, const int32_t* data, int64_t n, int32_t* out);
 

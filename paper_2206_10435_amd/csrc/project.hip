@@ -52,6 +52,19 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_proj_weights(const WorkItem* __res
   }
 }
 
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int off) {
+  const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, off);
+  const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), off);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// A projected entry's frequency: the saturating sum of w over the full
+// entries it groups (F.ecnt zeroed beforehand).  One thread per grouped
+// position, so a projected entry that groups many full entries (a heavy
+// value of the kept columns) is summed by many threads: the position's entry
+// is a binary search over the entries' starts, each wave sums its runs of
+// equal entries, and the run's last lane adds the sum with a saturating
+// compare-and-swap.
 __global__ void __launch_bounds__(GJ_BLOCK) k_proj_counts(const WorkItem* __restrict__ wl,
                                                           const TDesc* __restrict__ D, FPtrs F,
                                                           const int64_t* __restrict__ w, gjk::ProjArgs pa) {
@@ -60,13 +73,47 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_proj_counts(const WorkItem* __rest
   const int64_t M = F.cnt[it.t * CNT_STRIDE + CNT_M];
   const int64_t base = (int64_t)it.tile * GJ_TILE;
   const int64_t* wt = w + pa.full_off[it.t];
+  const int32_t* estart = F.estart + d.off;
+  const int ln = lane_id();
+  const int64_t wave0 = base + (threadIdx.x - ln);
   for (int r = 0; r < GJ_ROUNDS; ++r) {
-    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
-    if (e >= M) break;
-    const int64_t se = d.off + e;
-    uint64_t acc = 0;
-    for (int32_t x = F.estart[se]; x < F.eend[se]; ++x) acc = sadd(acc, (uint64_t)wt[F.perm[d.off + x]]);
-    F.ecnt[se] = (int64_t)acc;
+    if (wave0 + r * GJ_BLOCK >= d.n) break;  // wave-uniform
+    const int64_t x = base + r * GJ_BLOCK + threadIdx.x;
+    int32_t e = -1;
+    uint64_t v = 0;
+    if (x < d.n) {
+      int64_t lo = 0, hi = M;  // the last entry starting at or before x
+      while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (estart[mid] <= x)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      e = (int32_t)lo;
+      v = (uint64_t)wt[F.perm[d.off + x]];
+    }
+    const int32_t eprev = __shfl_up(e, 1);
+    const bool head = ln == 0 || eprev != e;
+    const uint64_t heads = __ballot(head);
+    const int sst = 63 - __clzll(heads & (ln == 63 ? ~0ull : ((2ull << ln) - 1)));
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint64_t u = shfl_up_u64(v, off);
+      if (ln - off >= sst) v = sadd(v, u);
+    }
+    const int32_t enext = __shfl_down(e, 1);
+    const bool tail = ln == 63 || enext != e;
+    if (tail && e >= 0) {
+      unsigned long long* dst = reinterpret_cast<unsigned long long*>(F.ecnt + d.off + e);
+      unsigned long long old = *dst;
+      while (true) {
+        const unsigned long long nv = sadd((uint64_t)old, v);
+        const unsigned long long prev = atomicCAS(dst, old, nv);
+        if (prev == old) break;
+        old = prev;
+      }
+    }
   }
 }
 
@@ -80,7 +127,8 @@ void proj_weights(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, co
 }
 
 void proj_counts(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F, const int64_t* w,
-                 const ProjArgs& pa) {
+                 const ProjArgs& pa, int64_t slots) {
+  fill_i64(s, F.ecnt, slots, 0);
   if (nwl > 0) hipLaunchKernelGGL(k_proj_counts, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, w, pa);
 }
 
@@ -215,7 +263,7 @@ gj_status gj_summarize_projected(gj_ctx* ctx, const gj_factors* fc, const uint32
   }
   launch_factors(pf->plan, pf->F, hs);
   const Plan& PP = pf->plan;
-  gjk::proj_counts(hs, PP.d_wl + PP.all.off, PP.all.n, PP.d_desc, pf->F, w, pa);
+  gjk::proj_counts(hs, PP.d_wl + PP.all.off, PP.all.n, PP.d_desc, pf->F, w, pa, PP.S);
 
   // 3. the summary of the projected factors
   gj_summary* s = new gj_summary(ctx);

@@ -125,6 +125,16 @@ def test_long_runs(gctx, oracle_mod, n, rows, mask):
     _check(gctx, oracle_mod, q, mask)
 
 
+def test_projected_entry_grouping_many_full_entries(gctx, oracle_mod):
+    """Keeping only A of T0(A, B): each of the 3 A values groups about a
+    thousand full (A, B) entries, so a projected frequency is summed over
+    many waves."""
+    q = W.chain_query(32, 9, 2, [40000, 4000], 2000, 0.0, name="wide_groups")
+    q.tables[0][0] = (q.tables[0][0] % 3).astype(np.int32)
+    _check(gctx, oracle_mod, q, [1, 0])
+    _check(gctx, oracle_mod, q, [3, 0])
+
+
 def test_values_of_unprojected_summary(gctx, oracle_mod):
     """On a full summary, run expansion writes every attribute of every result
     row: the oracle's sorted result mapped to its values."""
