@@ -239,3 +239,43 @@ def test_star_scaled_against_oracle(gctx, oracle_mod):
     out = torch.empty(Q * 6, dtype=torch.int64, device="cuda:0")
     assert gctx.desummarize(s, 0, Q, out) == Q
     assert np.array_equal(out.view(Q, 6).cpu().numpy(), o.canonical_result())
+
+
+def test_chain4_values_and_projection_full_size(gctx):
+    """The 4-table chain at full size with its payload: windows far into the
+    result (beyond 2^32 rows) of (a) the 8 payload columns equal the payload
+    at the row ids the row-id expansion writes for the same window, and (b)
+    the projection onto (A, B, C) equals the (A, B, C) values of the same
+    window of the full result (sorting by all columns and keeping a prefix
+    of them keeps the order and the multiplicities)."""
+    import torch
+
+    from paper_2206_10435_amd import gj
+
+    q = W.cfg2()
+    tabs = gj.to_device_tables(q)
+    f = gctx.build_factors(tabs, q.parent, q.sep_col, q.parent_col)
+    s = gctx.summarize(f)
+    Q = s.join_size
+    n = q.n_tables
+    pay = [[torch.from_numpy(c).to("cuda:0") for c in p] for p in q.payload]
+    cols = [(t, pay[t][i]) for t in range(n) for i in range(len(pay[t]))]
+    cs = gctx.colset(s, cols)
+    ps = gctx.summarize_projected(f, [3, 2, 0, 0])
+    assert ps.join_size == Q
+    rng = np.random.default_rng(5)
+    for first in (0, 3 * (1 << 28) + 99, int(rng.integers(1 << 33, Q - WIN)), Q - WIN // 3):
+        cnt = min(WIN, Q - first)
+        rid = torch.empty(cnt * n, dtype=torch.int64, device="cuda:0")
+        assert gctx.desummarize(s, first, cnt, rid) == cnt
+        tup = rid.view(cnt, n).cpu().numpy()
+        val = torch.empty(cnt * len(cols), dtype=torch.int32, device="cuda:0")
+        assert gctx.desummarize_values(s, cs, first, cnt, val) == cnt
+        got = val.view(cnt, len(cols)).cpu().numpy()
+        exp = np.stack([q.payload[t][i][tup[:, t]] for t in range(n) for i in range(len(q.payload[t]))], axis=1)
+        assert np.array_equal(got, exp), first
+        pv = torch.empty(cnt * 3, dtype=torch.int32, device="cuda:0")
+        assert gctx.desummarize_projected(ps, first, cnt, pv) == cnt
+        pexp = np.stack([q.tables[0][0][tup[:, 0]], q.tables[0][1][tup[:, 0]], q.tables[1][1][tup[:, 1]]], axis=1)
+        assert np.array_equal(pv.view(cnt, 3).cpu().numpy(), pexp), first
+        _say("values and projection window", first, "ok")
