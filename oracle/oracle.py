@@ -42,52 +42,62 @@ class _Q(C.Structure):
 _lib = None
 
 
+def _declare(L):
+    """Argument and return types of every exported oracle function."""
+    vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+    L.orc_open.restype = vp
+    L.orc_open.argtypes = [vp]
+    L.orc_close.argtypes = [vp]
+    L.orc_join_size.argtypes = [vp, vp]
+    L.orc_join_size.restype = C.c_int
+    L.orc_factor.argtypes = [vp, C.c_int, vp, vp, vp, vp]
+    L.orc_factor.restype = i64
+    L.orc_summary_table.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
+    L.orc_summary_table.restype = i64
+    L.orc_summary_edge.argtypes = [vp, C.c_int, vp, vp, vp]
+    L.orc_summary_edge.restype = i64
+    L.orc_fanouts.argtypes = [vp, C.c_int, vp]
+    L.orc_materialize.argtypes = [vp, i64, vp]
+    L.orc_materialize.restype = i64
+    L.orc_brute_force.argtypes = [vp, i64, vp]
+    L.orc_brute_force.restype = i64
+    L.orc_sort_canonical.argtypes = [vp, vp, i64]
+    L.orc_n_levels.argtypes = [vp]
+    L.orc_n_levels.restype = C.c_int
+    L.orc_gfjs.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.orc_unrank.argtypes = [vp, i64, vp]
+    L.orc_unrank.restype = C.c_int
+    L.orc_rank.argtypes = [vp, vp, vp]
+    L.orc_rank.restype = C.c_int
+    L.orc_weighted.argtypes = [vp, vp, vp]
+    L.orc_weighted.restype = C.c_double
+    L.orc_weighted_fd.argtypes = [vp, vp, C.c_int, vp, i64, C.c_double, C.c_int, vp]
+    L.orc_projection.argtypes = [vp, vp, vp, vp]
+    L.orc_projection.restype = C.c_int
+    L.orc_projected_table.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp]
+    L.orc_projected_table.restype = i64
+    L.orc_nat_open.restype = vp
+    L.orc_nat_open.argtypes = [i32, vp, vp, vp, vp]
+    L.orc_nat_close.argtypes = [vp]
+    L.orc_nat_materialize.argtypes = [vp, i64, vp]
+    L.orc_nat_materialize.restype = i64
+    L.orc_nat_brute_force.argtypes = [vp, i64, vp]
+    L.orc_nat_brute_force.restype = i64
+    return L
+
+
+def load_at(path: str):
+    """The oracle library at `path` (a build of these sources elsewhere, e.g.
+    a sanitizer build or a test's scratch copy), with its types declared."""
+    return _declare(C.CDLL(path))
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
-        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
-        L.orc_open.restype = vp
-        L.orc_open.argtypes = [vp]
-        L.orc_close.argtypes = [vp]
-        L.orc_join_size.argtypes = [vp, vp]
-        L.orc_join_size.restype = C.c_int
-        L.orc_factor.argtypes = [vp, C.c_int, vp, vp, vp, vp]
-        L.orc_factor.restype = i64
-        L.orc_summary_table.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
-        L.orc_summary_table.restype = i64
-        L.orc_summary_edge.argtypes = [vp, C.c_int, vp, vp, vp]
-        L.orc_summary_edge.restype = i64
-        L.orc_fanouts.argtypes = [vp, C.c_int, vp]
-        L.orc_materialize.argtypes = [vp, i64, vp]
-        L.orc_materialize.restype = i64
-        L.orc_brute_force.argtypes = [vp, i64, vp]
-        L.orc_brute_force.restype = i64
-        L.orc_sort_canonical.argtypes = [vp, vp, i64]
-        L.orc_n_levels.argtypes = [vp]
-        L.orc_n_levels.restype = C.c_int
-        L.orc_gfjs.argtypes = [vp, vp, i64, vp, vp, vp]
-        L.orc_unrank.argtypes = [vp, i64, vp]
-        L.orc_unrank.restype = C.c_int
-        L.orc_rank.argtypes = [vp, vp, vp]
-        L.orc_rank.restype = C.c_int
-        L.orc_weighted.argtypes = [vp, vp, vp]
-        L.orc_weighted.restype = C.c_double
-        L.orc_weighted_fd.argtypes = [vp, vp, C.c_int, vp, i64, C.c_double, C.c_int, vp]
-        L.orc_projection.argtypes = [vp, vp, vp, vp]
-        L.orc_projection.restype = C.c_int
-        L.orc_projected_table.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp]
-        L.orc_projected_table.restype = i64
-        L.orc_nat_open.restype = vp
-        L.orc_nat_open.argtypes = [i32, vp, vp, vp, vp]
-        L.orc_nat_close.argtypes = [vp]
-        L.orc_nat_materialize.argtypes = [vp, i64, vp]
-        L.orc_nat_materialize.restype = i64
-        L.orc_nat_brute_force.argtypes = [vp, i64, vp]
-        L.orc_nat_brute_force.restype = i64
-        _lib = L
+        _lib = _declare(C.CDLL(LIB))
     return _lib
 
 
@@ -98,8 +108,10 @@ def _p(a: np.ndarray):
 class Oracle:
     """Row-level reference for one query (see gj_oracle.cpp for definitions)."""
 
-    def __init__(self, q):
+    def __init__(self, q, L=None):
+        """`L`: an oracle library from load_at (default: the one built here)."""
         self.q = q
+        self.L = L if L is not None else lib()
         n = q.n_tables
         self._cols = [[np.ascontiguousarray(c, dtype=np.int32) for c in tb] for tb in q.tables]
         self._nrows = np.array([q.n_rows(t) for t in range(n)], dtype=np.int64)
@@ -114,11 +126,11 @@ class Oracle:
         self._pcol = np.array(q.parent_col, dtype=np.int32)
         self._qs = _Q(n, self._nrows.ctypes.data, self._nkeys.ctypes.data, ptrs.ctypes.data,
                       self._par.ctypes.data, self._sep.ctypes.data, self._pcol.ctypes.data)
-        self.h = lib().orc_open(C.byref(self._qs))
+        self.h = self.L.orc_open(C.byref(self._qs))
 
     def close(self):
         if self.h:
-            lib().orc_close(self.h)
+            self.L.orc_close(self.h)
             self.h = None
 
     def __del__(self):
@@ -134,7 +146,7 @@ class Oracle:
     def join_size(self):
         """(|Q|, overflow flag)."""
         out = np.zeros(1, dtype=np.int64)
-        rc = lib().orc_join_size(self.h, _p(out))
+        rc = self.L.orc_join_size(self.h, _p(out))
         return int(out[0]), rc == OVERFLOW
 
     def factor(self, t):
@@ -144,7 +156,7 @@ class Oracle:
         cnt = np.zeros(max(N, 1), dtype=np.int64)
         start = np.zeros(max(N, 1), dtype=np.int64)
         perm = np.zeros(max(N, 1), dtype=np.int32)
-        M = lib().orc_factor(self.h, t, _p(keys), _p(cnt), _p(start), _p(perm))
+        M = self.L.orc_factor(self.h, t, _p(keys), _p(cnt), _p(start), _p(perm))
         return dict(keys=keys[:M], count=cnt[:M], start=start[:M], perm=perm[:N])
 
     def summary_table(self, t):
@@ -153,7 +165,7 @@ class Oracle:
         cap = max(N, 1)
         keys = np.zeros((cap, k), dtype=np.int32)
         arrs = [np.zeros(cap, dtype=np.int64) for _ in range(4)]
-        m = lib().orc_summary_table(self.h, t, _p(keys), *[_p(a) for a in arrs])
+        m = self.L.orc_summary_table(self.h, t, _p(keys), *[_p(a) for a in arrs])
         return dict(keys=keys[:m], c=arrs[0][:m], U=arrs[1][:m], D=arrs[2][:m], F=arrs[3][:m])
 
     def summary_edge(self, t):
@@ -162,12 +174,12 @@ class Oracle:
         s = np.zeros(cap, dtype=np.int32)
         M = np.zeros(cap, dtype=np.int64)
         D = np.zeros(cap, dtype=np.int64)
-        m = lib().orc_summary_edge(self.h, t, _p(s), _p(M), _p(D))
+        m = self.L.orc_summary_edge(self.h, t, _p(s), _p(M), _p(D))
         return dict(s=s[:m], M=M[:m], D=D[:m])
 
     def fanouts(self, t):
         out = np.zeros(max(self.q.n_rows(t), 1), dtype=np.int64)
-        lib().orc_fanouts(self.h, t, _p(out))
+        self.L.orc_fanouts(self.h, t, _p(out))
         return out[: self.q.n_rows(t)]
 
     def materialize(self, limit=None):
@@ -176,17 +188,17 @@ class Oracle:
         if limit > 200_000_000:
             raise MemoryError(f"refusing to materialize {limit} tuples in host memory")
         out = np.zeros((max(limit, 1), self.n), dtype=np.int32)
-        m = lib().orc_materialize(self.h, int(limit), _p(out))
+        m = self.L.orc_materialize(self.h, int(limit), _p(out))
         return out[:m]
 
     def brute_force(self, limit=10**7):
         out = np.zeros((limit, self.n), dtype=np.int32)
-        m = lib().orc_brute_force(self.h, int(limit), _p(out))
+        m = self.L.orc_brute_force(self.h, int(limit), _p(out))
         return out[:m]
 
     def sort_canonical(self, tuples):
         t = np.ascontiguousarray(tuples, dtype=np.int32).copy()
-        lib().orc_sort_canonical(self.h, _p(t), int(t.shape[0]))
+        self.L.orc_sort_canonical(self.h, _p(t), int(t.shape[0]))
         return t
 
     def canonical_result(self):
@@ -195,17 +207,17 @@ class Oracle:
     def gfjs(self, sorted_tuples):
         """Per result column: list of (value, freq) runs (Definition 1 per prefix)."""
         st = np.ascontiguousarray(sorted_tuples, dtype=np.int32)
-        L = lib().orc_n_levels(self.h)
+        L = self.L.orc_n_levels(self.h)
         cnt = st.shape[0]
         vals = np.zeros((L, max(cnt, 1)), dtype=np.int32)
         freqs = np.zeros((L, max(cnt, 1)), dtype=np.int64)
         nr = np.zeros(L, dtype=np.int64)
-        lib().orc_gfjs(self.h, _p(st), cnt, _p(vals), _p(freqs), _p(nr))
+        self.L.orc_gfjs(self.h, _p(st), cnt, _p(vals), _p(freqs), _p(nr))
         return [(vals[i, : nr[i]].copy(), freqs[i, : nr[i]].copy()) for i in range(L)]
 
     def unrank(self, R):
         out = np.zeros(self.n, dtype=np.int32)
-        rc = lib().orc_unrank(self.h, int(R), _p(out))
+        rc = self.L.orc_unrank(self.h, int(R), _p(out))
         if rc != 0:
             raise IndexError(R)
         return out
@@ -213,7 +225,7 @@ class Oracle:
     def rank(self, tup):
         t = np.ascontiguousarray(tup, dtype=np.int32)
         out = np.zeros(1, dtype=np.int64)
-        rc = lib().orc_rank(self.h, _p(t), _p(out))
+        rc = self.L.orc_rank(self.h, _p(t), _p(out))
         if rc != 0:
             raise ValueError("tuple is not in the join result")
         return int(out[0])
@@ -230,7 +242,7 @@ class Oracle:
         ws, ptrs = self._wptrs(w)
         g = [np.zeros(max(self.q.n_rows(t), 1)) for t in range(self.n)] if grads else None
         gp = np.array([x.ctypes.data for x in g], dtype=np.uint64) if grads else None
-        W = lib().orc_weighted(self.h, _p(ptrs) if ptrs is not None else None,
+        W = self.L.orc_weighted(self.h, _p(ptrs) if ptrs is not None else None,
                                _p(gp) if gp is not None else None)
         return W, ([x[: self.q.n_rows(t)] for t, x in enumerate(g)] if grads else None)
 
@@ -238,7 +250,7 @@ class Oracle:
         ws, ptrs = self._wptrs(w)
         rows = np.ascontiguousarray(rows, dtype=np.int64)
         out = np.zeros(len(rows))
-        lib().orc_weighted_fd(self.h, _p(ptrs), int(t), _p(rows), len(rows), float(hfrac),
+        self.L.orc_weighted_fd(self.h, _p(ptrs), int(t), _p(rows), len(rows), float(hfrac),
                               int(threads), _p(out))
         return out
 
@@ -249,7 +261,7 @@ class Oracle:
         m = np.ascontiguousarray(mask, dtype=np.uint32)
         out = np.zeros(self.n, dtype=np.uint32)
         kept = np.zeros(self.n, dtype=np.int32)
-        rc = lib().orc_projection(self.h, _p(m), _p(out), _p(kept))
+        rc = self.L.orc_projection(self.h, _p(m), _p(out), _p(kept))
         return rc == 0, out, kept.astype(bool)
 
     def projected_columns(self, mask):
@@ -288,7 +300,7 @@ class Oracle:
         cap = max(self.q.n_rows(t), 1)
         keys = np.zeros((cap, max(k, 1)), dtype=np.int32)
         arrs = [np.zeros(cap, dtype=np.int64) for _ in range(4)]
-        e = lib().orc_projected_table(self.h, _p(m), int(t), _p(keys), *[_p(a) for a in arrs])
+        e = self.L.orc_projected_table(self.h, _p(m), int(t), _p(keys), *[_p(a) for a in arrs])
         return dict(keys=keys[:e, :k], c=arrs[0][:e], U=arrs[1][:e], D=arrs[2][:e], F=arrs[3][:e])
 
 
