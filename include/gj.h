@@ -28,7 +28,10 @@
  *     allocated through the context's allocator; output chunks are owned by
  *     the caller.
  *   - Every entry point returns a gj_status; out-parameters are written only
- *     on GJ_OK.  gj_last_error() gives a message for the calling thread.
+ *     on GJ_OK.  gj_last_error(ctx) gives the message of the last failed call
+ *     made with that context (or with an object made by it); calls that take
+ *     no context (gj_validate, gj_junction_tree_build) leave theirs per thread,
+ *     returned for ctx = NULL.
  *   - Join graph: table 0 is the root; for t >= 1, parent[t] < t and table t
  *     joins its parent on  key[t][sep_col[t]] == key[parent[t]][parent_col[t]].
  *     Composite separators and cyclic queries are rejected (GJ_E_GRAPH).
@@ -79,8 +82,15 @@ typedef void (*gj_free_fn)(void* ptr, void* user);
 gj_status gj_ctx_create(int device, void* hip_stream, gj_alloc_fn alloc, gj_free_fn free_fn, void* user,
                         gj_ctx** out);
 void gj_ctx_destroy(gj_ctx* ctx);
-/* Message describing the last error on the calling thread ("" if none). */
-const char* gj_last_error(void);
+/* Message of the last failed call made with `ctx` or with a factor set,
+ * summary, column set, batch, potential or saved state made by it ("" if
+ * none); ctx = NULL: the last failure on the calling thread, which is where
+ * calls without a context (gj_validate, gj_junction_tree_build, and a
+ * gj_ctx_create that fails) record theirs.  The string lives until the next
+ * failure recorded in the same place.  A context is used by one thread at a
+ * time (its calls are ordered on one stream), so its message is not shared
+ * between threads. */
+const char* gj_last_error(const gj_ctx* ctx);
 
 /* One input table: n_keys int32 key columns (device pointers, SoA, n_rows each).
  * `keys` itself is a host array of n_keys device pointers.  Only the columns
@@ -113,15 +123,19 @@ gj_status gj_build_factors(gj_ctx* ctx, const gj_table* tables, const gj_join_gr
 
 /* View of table t's factor (device pointers valid while the factors live):
  *   keys[c]  int32[n_entries]  key column c (declared order) of every entry
+ *   count    int64[n_entries]  the entry's frequency (the potential's count,
+ *                              Sec. 3.2) = end - start
  *   start    int32[n_entries]  first position of the entry's rows in perm
- *   end      int32[n_entries]  one past the last; end - start is the entry's
- *                              frequency (the potential's count)
- *   perm     int32[n_rows]     row ids grouped by entry, ascending inside one */
+ *   end      int32[n_entries]  one past the last
+ *   perm     int32[n_rows]     row ids grouped by entry, ascending inside one
+ * The first view of a factor set synchronizes the stream (entry counts) and
+ * fills `count` for every table with one small kernel. */
 typedef struct {
   int64_t n_entries;
   int64_t n_rows;
   int32_t n_keys;
   const int32_t* keys[GJ_MAX_KEYS];
+  const int64_t* count;
   const int32_t* start;
   const int32_t* end;
   const int32_t* perm;
@@ -141,6 +155,28 @@ void gj_free_factors(gj_factors* f);
  * excluded, which is how unneeded intermediate results are avoided).
  * `join_size` (host) receives the join size. */
 gj_status gj_summarize(gj_ctx* ctx, const gj_factors* f, gj_summary** out, int64_t* join_size);
+
+/* The same upward and downward passes for n_queries factor sets (each made
+ * by gj_build_factors, all distinct, all on ctx) with nothing read back to
+ * the host: every query's kernels are launched in stream order and query i's
+ * join size and status (GJ_OK, or GJ_E_OVERFLOW when it is >= 2^63-1) are
+ * written to d_join_sizes[i] (int64) and d_status[i] (int32), device arrays
+ * owned by the caller.  outs (host array of n_queries):
+ *   outs[i] == NULL on entry: a summary of factors[i] is allocated through the
+ *     context's allocator and returned in outs[i];
+ *   outs[i] == a summary made earlier for factors[i] (by gj_summarize or by
+ *     this call): it is recomputed in place, allocating nothing.
+ * A call that is given every summary allocates nothing and never waits for
+ * the device, so it can be recorded into a HIP graph (capture the context's
+ * stream, call, end the capture); each replay recomputes every summary from
+ * the factors' current contents.  The host side of a summary computed this
+ * way (entry counts, join size) is read with one synchronization by its first
+ * view, expansion, save or gj_summary_join_size, which return GJ_E_OVERFLOW
+ * for a query that overflowed.  Arguments are checked before anything is
+ * launched: null pointers, factors of another context or of a batch, the same
+ * factors twice, a summary made for other factors -> GJ_E_INVALID. */
+gj_status gj_summarize_batch(gj_ctx* ctx, const gj_factors* const* factors, int32_t n_queries, gj_summary** outs,
+                             int64_t* d_join_sizes, int32_t* d_status);
 
 /* Surviving entries of table t in factor order (device pointers):
  *   keys[c] int32, c/U/D/F int64; F = c*U*D is the entry's run length in the
@@ -168,6 +204,7 @@ typedef struct {
   const int64_t* D;
 } gj_edge_view;
 gj_status gj_summary_edge(const gj_summary* s, int32_t t, gj_edge_view* v);
+/* Join size of a summary (-1: NULL, or its query overflowed). */
 int64_t gj_summary_join_size(const gj_summary* s);
 void gj_free_summary(gj_summary* s);
 
@@ -391,6 +428,25 @@ const int32_t* gj_batch_status(const gj_batch* b);
  * or relaunched; do not free it). */
 gj_status gj_batch_summary(gj_batch* b, int32_t q, const gj_summary** out);
 void gj_free_batch(gj_batch* b);
+
+/* Launch shape that gj_desummarize (n_cols = 0, rowid_bytes 4 or 8) or
+ * gj_desummarize_values (n_cols value columns, rowid_bytes 4) uses for n_rows
+ * rows of an n_tables-table summary under `tune` (NULL: defaults).  Host
+ * only, no device work: lets tests and tuners check every setting's launch
+ * against the kernel's limits.  GJ_E_INVALID for arguments or shapes the
+ * kernel does not support (the expansion entry points then fail the same way). */
+typedef struct {
+  int32_t stage;           /* tuples per lane per LDS staging round */
+  int32_t tuples_per_lane; /* tuples a lane writes (a multiple of stage) */
+  int32_t kernel_tables;   /* table count of the kernel instance (exact up to 8, else 16) */
+  int32_t change_bits;     /* bits of the per-round change mask = stage * kernel_tables (<= 64) */
+  int32_t seg_bytes;       /* bytes a lane stages per round (whole 16-byte units) */
+  int64_t blocks;          /* 256-thread blocks (a multiple of 8) */
+  int64_t lds_bytes;       /* dynamic LDS allocated per block */
+  int64_t lds_used;        /* LDS the actual columns use (<= lds_bytes) */
+} gj_desum_launch;
+gj_status gj_desum_launch_config(int32_t n_tables, int32_t rowid_bytes, int32_t n_cols, int64_t n_rows,
+                                 const gj_tune* tune, gj_desum_launch* out);
 
 /* Plumbing for bindings and tests: copies `bytes` of device memory to host
  * memory on the context stream and waits for it. */

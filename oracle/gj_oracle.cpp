@@ -203,6 +203,32 @@ std::map<std::vector<int32_t>, std::vector<int32_t>> group_by(const State& s, in
   return g;
 }
 
+// The same group-by as a sorted row list: the rows of t sorted by (key tuple
+// in canonical column order, row id), split where the key tuple changes.
+// Group g is rows[start[g] .. start[g+1]); its key is that of any of its rows.
+struct SortedGroups {
+  std::vector<int32_t> rows;
+  std::vector<int64_t> start;  // groups + 1
+};
+SortedGroups sorted_groups(const State& s, int t) {
+  SortedGroups g;
+  const std::vector<int> cc = s.canon_cols(t);
+  auto less_key = [&](int32_t a, int32_t b) {
+    for (int c : cc) {
+      const int32_t x = s.key(t, c, a), y = s.key(t, c, b);
+      if (x != y) return x < y;
+    }
+    return false;
+  };
+  g.rows.resize(s.N[t]);
+  std::iota(g.rows.begin(), g.rows.end(), 0);
+  std::sort(g.rows.begin(), g.rows.end(), [&](int32_t a, int32_t b) { return less_key(a, b) || (!less_key(b, a) && a < b); });
+  for (int64_t i = 0; i < s.N[t]; ++i)
+    if (i == 0 || less_key(g.rows[i - 1], g.rows[i])) g.start.push_back(i);
+  g.start.push_back(s.N[t]);
+  return g;
+}
+
 // Sort key of a result tuple: attribute values in result-column order, then
 // the row ids in table order.
 std::vector<int64_t> tuple_sort_key(const State& s, const int32_t* rows) {
@@ -303,21 +329,17 @@ int orc_join_size(void* h, int64_t* out) {
 // first position in the grouped row list, and the grouped row list itself.
 int64_t orc_factor(void* h, int t, int32_t* keys, int64_t* cnt, int64_t* start, int32_t* perm) {
   State& s = *(State*)h;
-  auto g = group_by(s, t);
-  std::vector<int> cc = s.canon_cols(t);
-  int64_t e = 0, pos = 0;
-  for (auto& kv : g) {
+  const SortedGroups g = sorted_groups(s, t);
+  const int64_t M = (int64_t)g.start.size() - 1;
+  for (int64_t e = 0; e < M; ++e) {
+    const int32_t r0 = g.rows[g.start[e]];
     if (keys)
-      for (size_t i = 0; i < cc.size(); ++i) keys[e * s.K[t] + cc[i]] = kv.first[i];
-    if (cnt) cnt[e] = (int64_t)kv.second.size();
-    if (start) start[e] = pos;
-    for (int32_t r : kv.second) {
-      if (perm) perm[pos] = r;
-      ++pos;
-    }
-    ++e;
+      for (int c = 0; c < s.K[t]; ++c) keys[e * s.K[t] + c] = s.key(t, c, r0);
+    if (cnt) cnt[e] = g.start[e + 1] - g.start[e];
+    if (start) start[e] = g.start[e];
   }
-  return e;
+  if (perm) std::copy(g.rows.begin(), g.rows.end(), perm);
+  return M;
 }
 
 // Surviving entries of table t (frequency in the result F > 0) with
@@ -325,17 +347,17 @@ int64_t orc_factor(void* h, int t, int32_t* keys, int64_t* cnt, int64_t* start, 
 // D = completions outside (up), F = sum of the rows' fan-outs.
 int64_t orc_summary_table(void* h, int t, int32_t* keys, int64_t* c, int64_t* U, int64_t* D, int64_t* F) {
   State& s = *(State*)h;
-  auto g = group_by(s, t);
-  std::vector<int> cc = s.canon_cols(t);
+  const SortedGroups g = sorted_groups(s, t);
+  const int64_t M = (int64_t)g.start.size() - 1;
   int64_t e = 0;
-  for (auto& kv : g) {
+  for (int64_t x = 0; x < M; ++x) {
     i128 f = 0;
-    for (int32_t r : kv.second) f = sadd(f, smul(s.down[t][r], s.up[t][r]));
+    for (int64_t i = g.start[x]; i < g.start[x + 1]; ++i) f = sadd(f, smul(s.down[t][g.rows[i]], s.up[t][g.rows[i]]));
     if (f == 0) continue;
-    int32_t r0 = kv.second[0];
+    const int32_t r0 = g.rows[g.start[x]];
     if (keys)
-      for (size_t i = 0; i < cc.size(); ++i) keys[e * s.K[t] + cc[i]] = kv.first[i];
-    if (c) c[e] = (int64_t)kv.second.size();
+      for (int cc = 0; cc < s.K[t]; ++cc) keys[e * s.K[t] + cc] = s.key(t, cc, r0);
+    if (c) c[e] = g.start[x + 1] - g.start[x];
     if (U) U[e] = to64(s.down[t][r0]);
     if (D) D[e] = to64(s.up[t][r0]);
     if (F) F[e] = to64(f);

@@ -15,6 +15,10 @@
 namespace gjh {
 
 static thread_local std::string g_err;
+static thread_local gj_ctx* g_cur = nullptr;
+
+CtxScope::CtxScope(const gj_ctx* c) : prev(g_cur) { g_cur = const_cast<gj_ctx*>(c); }
+CtxScope::~CtxScope() { g_cur = prev; }
 
 void set_error(const char* fmt, ...) {
   char buf[1024];
@@ -23,6 +27,7 @@ void set_error(const char* fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   g_err = buf;
+  if (g_cur) g_cur->err = buf;
 }
 
 gj_status check(hipError_t e, const char* what) {
@@ -484,6 +489,28 @@ gj_status read_counters(const Plan& P, const FPtrs& F, hipStream_t s, std::vecto
   return check(hipStreamSynchronize(s), "counters");
 }
 
+gj_status summary_host(const gj_summary* sc) {
+  gj_summary* s = const_cast<gj_summary*>(sc);
+  if (s->host_stale) {
+    hipStream_t hs = s->ctx->stream;
+    int64_t q = 0;
+    int32_t qs = 0;
+    gj_status st;
+    if ((st = check(hipMemcpyAsync(&q, s->S.qsize + s->query, 8, hipMemcpyDeviceToHost, hs), "join size")) ||
+        (st = check(hipMemcpyAsync(&qs, s->S.qstatus + s->query, 4, hipMemcpyDeviceToHost, hs), "join size")) ||
+        (st = read_counters(s->f->plan, s->f->F, hs, s->cnt_host)))
+      return st;
+    s->join_size = q;
+    s->status = qs;
+    s->host_stale = false;
+  }
+  if (s->status == GJ_E_OVERFLOW) {
+    set_error("join size does not fit below 2^63-1");
+    return GJ_E_OVERFLOW;
+  }
+  return GJ_OK;
+}
+
 }  // namespace gjh
 
 using namespace gjh;
@@ -493,7 +520,7 @@ using namespace gjh;
 // ===========================================================================
 extern "C" {
 
-const char* gj_last_error(void) { return g_err.c_str(); }
+const char* gj_last_error(const gj_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
 
 gj_status gj_ctx_create(int device, void* hip_stream, gj_alloc_fn alloc, gj_free_fn free_fn, void* user,
                         gj_ctx** out) {
@@ -520,6 +547,7 @@ gj_status gj_ctx_create(int device, void* hip_stream, gj_alloc_fn alloc, gj_free
 void gj_ctx_destroy(gj_ctx* ctx) { delete ctx; }
 
 gj_status gj_ctx_set_tune(gj_ctx* ctx, const gj_tune* tune) {
+  GJ_SCOPE(ctx);
   if (!ctx || !tune) {
     set_error("gj_ctx_set_tune: null argument");
     return GJ_E_INVALID;
@@ -538,6 +566,7 @@ gj_status gj_ctx_set_tune(gj_ctx* ctx, const gj_tune* tune) {
 gj_status gj_validate(const gj_table* tables, const gj_join_graph* graph) { return validate_one(tables, graph); }
 
 gj_status gj_build_factors(gj_ctx* ctx, const gj_table* tables, const gj_join_graph* graph, gj_factors** out) {
+  GJ_SCOPE(ctx);
   if (!ctx || !out) {
     set_error("gj_build_factors: null argument");
     return GJ_E_INVALID;
@@ -567,15 +596,25 @@ static gj_status ensure_counters(const gj_factors* f) {
 }
 
 gj_status gj_factor_table(const gj_factors* f, int32_t t, gj_factor_view* v) {
+  GJ_SCOPE(f ? f->ctx : nullptr);
   if (!f || !v || t < 0 || t >= f->plan.nt) {
     set_error("gj_factor_table: bad argument");
     return GJ_E_INVALID;
   }
   gj_status st = ensure_counters(f);
   if (st) return st;
+  if (!f->ecount) {
+    gj_factors* m = const_cast<gj_factors*>(f);
+    int64_t* ec = m->arena.get_n<int64_t>(m->plan.S);
+    if (!ec) return GJ_E_OOM;
+    gjk::entry_counts(m->ctx->stream, m->plan.d_wl + m->plan.all.off, m->plan.all.n, m->plan.d_desc, m->F, ec);
+    if ((st = check(hipGetLastError(), "entry counts"))) return st;
+    m->ecount = ec;
+  }
   const TDesc& d = f->plan.td[t];
   gj_factor_view r{};
   r.n_entries = f->cnt_host[t * CNT_STRIDE + CNT_M];
+  r.count = f->ecount + d.off;
   r.n_rows = d.n;
   r.n_keys = d.k;
   for (int c = 0; c < d.k; ++c) r.keys[c] = f->F.ekey + d.key_off + (int64_t)c * d.n;
@@ -592,6 +631,7 @@ void gj_free_factors(gj_factors* f) {
 }
 
 gj_status gj_summarize(gj_ctx* ctx, const gj_factors* fc, gj_summary** out, int64_t* join_size) {
+  GJ_SCOPE(ctx);
   if (!ctx || !fc || !out) {
     set_error("gj_summarize: null argument");
     return GJ_E_INVALID;
@@ -631,6 +671,61 @@ gj_status gj_summarize(gj_ctx* ctx, const gj_factors* fc, gj_summary** out, int6
   return GJ_OK;
 }
 
+gj_status gj_summarize_batch(gj_ctx* ctx, const gj_factors* const* factors, int32_t n_queries, gj_summary** outs,
+                             int64_t* d_join_sizes, int32_t* d_status) {
+  GJ_SCOPE(ctx);
+  if (!ctx || n_queries < 0 || (n_queries > 0 && (!factors || !outs || !d_join_sizes || !d_status))) {
+    set_error("gj_summarize_batch: bad argument");
+    return GJ_E_INVALID;
+  }
+  // validate everything before launching anything
+  for (int32_t i = 0; i < n_queries; ++i) {
+    const gj_factors* f = factors[i];
+    if (!f || f->ctx != ctx || f->plan.nq != 1) {
+      set_error("gj_summarize_batch: factors %d are null, from another context, or not one query's", i);
+      return GJ_E_INVALID;
+    }
+    for (int32_t j = 0; j < i; ++j)
+      if (factors[j] == f) {
+        set_error("gj_summarize_batch: factors %d and %d are the same set", j, i);
+        return GJ_E_INVALID;
+      }
+    const gj_summary* o = outs[i];
+    if (o && (o->f != f || o->borrowed || o->projected || o->query != 0)) {
+      set_error("gj_summarize_batch: summary %d was not made for factors %d", i, i);
+      return GJ_E_INVALID;
+    }
+  }
+  // summaries to allocate (only when the caller passed none)
+  std::vector<gj_summary*> fresh(n_queries, nullptr);
+  for (int32_t i = 0; i < n_queries; ++i) {
+    if (outs[i]) continue;
+    gj_factors* f = const_cast<gj_factors*>(factors[i]);
+    gj_summary* s = new gj_summary(ctx);
+    s->f = f;
+    f->refs++;
+    fresh[i] = s;
+    if (gj_status st = alloc_summary(f->plan, s->arena, s->S)) {
+      for (gj_summary* x : fresh) gj_free_summary(x);
+      return st;
+    }
+  }
+  hipStream_t hs = ctx->stream;
+  for (int32_t i = 0; i < n_queries; ++i) {
+    gj_summary* s = outs[i] ? outs[i] : fresh[i];
+    launch_summary(s->f->plan, s->f->F, s->S, hs);
+    gjk::export_status(hs, s->S.qsize, s->S.qstatus, d_join_sizes + i, d_status + i);
+    s->host_stale = true;
+  }
+  if (gj_status st = check(hipGetLastError(), "summary kernels")) {
+    for (gj_summary* x : fresh) gj_free_summary(x);
+    return st;
+  }
+  for (int32_t i = 0; i < n_queries; ++i)
+    if (fresh[i]) outs[i] = fresh[i];
+  return GJ_OK;
+}
+
 static const TDesc* summary_table_desc(const gj_summary* s, int32_t t) {
   const Plan& P = s->f->plan;
   int base = P.qfirst[s->query];
@@ -640,11 +735,13 @@ static const TDesc* summary_table_desc(const gj_summary* s, int32_t t) {
 }
 
 gj_status gj_summary_table(const gj_summary* s, int32_t t, gj_summary_view* v) {
+  GJ_SCOPE(s ? s->ctx : nullptr);
   const TDesc* d = s && v ? summary_table_desc(s, t) : nullptr;
   if (!d) {
     set_error("gj_summary_table: bad argument");
     return GJ_E_INVALID;
   }
+  if (gj_status st = summary_host(s)) return st;
   const int gt = (int)(d - s->f->plan.td.data());
   gj_summary_view r{};
   r.n_entries = s->cnt_host[gt * CNT_STRIDE + CNT_MC];
@@ -660,11 +757,13 @@ gj_status gj_summary_table(const gj_summary* s, int32_t t, gj_summary_view* v) {
 }
 
 gj_status gj_summary_edge(const gj_summary* s, int32_t t, gj_edge_view* v) {
+  GJ_SCOPE(s ? s->ctx : nullptr);
   const TDesc* d = s && v && t >= 1 ? summary_table_desc(s, t) : nullptr;
   if (!d) {
     set_error("gj_summary_edge: bad argument (edges exist for tables >= 1)");
     return GJ_E_INVALID;
   }
+  if (gj_status st = summary_host(s)) return st;
   const int gt = (int)(d - s->f->plan.td.data());
   gj_edge_view r{};
   r.n = s->cnt_host[gt * CNT_STRIDE + CNT_GC];
@@ -676,6 +775,7 @@ gj_status gj_summary_edge(const gj_summary* s, int32_t t, gj_edge_view* v) {
 }
 
 gj_status gj_download(gj_ctx* ctx, void* host_dst, const void* dev_src, size_t bytes) {
+  GJ_SCOPE(ctx);
   if (!ctx || (bytes && (!host_dst || !dev_src))) {
     set_error("gj_download: null argument");
     return GJ_E_INVALID;
@@ -686,7 +786,11 @@ gj_status gj_download(gj_ctx* ctx, void* host_dst, const void* dev_src, size_t b
   return check(hipStreamSynchronize(ctx->stream), "download");
 }
 
-int64_t gj_summary_join_size(const gj_summary* s) { return s ? s->join_size : -1; }
+int64_t gj_summary_join_size(const gj_summary* s) {
+  if (!s) return -1;
+  GJ_SCOPE(s->ctx);
+  return summary_host(s) == GJ_OK ? s->join_size : -1;
+}
 
 void gj_free_summary(gj_summary* s) {
   if (!s || s->borrowed) return;
@@ -730,6 +834,7 @@ extern "C" {
 
 gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, int64_t n_rows, int32_t rowid_bytes,
                          void* out, int64_t* n_written) {
+  GJ_SCOPE(ctx);
   if (!ctx || !s || (rowid_bytes != 4 && rowid_bytes != 8) || n_rows < 0 || first_row < 0) {
     set_error("gj_desummarize: bad argument");
     return GJ_E_INVALID;
@@ -739,6 +844,7 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
               "use gj_desummarize_projected");
     return GJ_E_INVALID;
   }
+  if (gj_status st = summary_host(s)) return st;
   if (first_row > s->join_size) {
     set_error("first_row %lld beyond the join size %lld", (long long)first_row, (long long)s->join_size);
     return GJ_E_RANGE;
@@ -765,6 +871,7 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
 
 gj_status gj_colset_create(gj_ctx* ctx, const gj_summary* s, int32_t n_cols, const int32_t* tab,
                            const int32_t* const* data, gj_colset** out) {
+  GJ_SCOPE(ctx);
   if (!ctx || !s || !out || n_cols < 1 || n_cols > GJ_MAX_OUT_COLS || !tab || !data) {
     set_error("gj_colset_create: bad argument (1 <= n_cols <= %d)", GJ_MAX_OUT_COLS);
     return GJ_E_INVALID;
@@ -819,6 +926,7 @@ void gj_free_colset(gj_colset* c) {
 
 gj_status gj_desummarize_values(gj_ctx* ctx, const gj_summary* s, const gj_colset* cs, int64_t first_row,
                                 int64_t n_rows, int32_t* out, int64_t* n_written) {
+  GJ_SCOPE(ctx);
   if (!ctx || !s || !cs || n_rows < 0 || first_row < 0) {
     set_error("gj_desummarize_values: bad argument");
     return GJ_E_INVALID;
@@ -827,6 +935,7 @@ gj_status gj_desummarize_values(gj_ctx* ctx, const gj_summary* s, const gj_colse
     set_error("gj_desummarize_values: the column set was made for another summary's factors");
     return GJ_E_INVALID;
   }
+  if (gj_status st = summary_host(s)) return st;
   if (first_row > s->join_size) {
     set_error("first_row %lld beyond the join size %lld", (long long)first_row, (long long)s->join_size);
     return GJ_E_RANGE;

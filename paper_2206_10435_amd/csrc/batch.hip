@@ -20,6 +20,7 @@ struct gj_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
+  hipEvent_t done = nullptr;  // end of a launch on a stream other than the context's
   std::vector<int64_t> cnt_host;
   bool counters_valid = false;
 };
@@ -29,6 +30,7 @@ static void batch_destroy(gj_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->done) (void)hipEventDestroy(b->done);
   for (gj_summary* v : b->views) delete v;
   if (b->s) {
     b->s->borrowed = false;
@@ -42,6 +44,7 @@ extern "C" {
 
 gj_status gj_batch_create(gj_ctx* ctx, int32_t n_queries, const int32_t* q_off, const gj_table* tables,
                           const gj_join_graph* graphs, const gj_tune* tune, gj_batch** out) {
+  GJ_SCOPE(ctx);
   if (!ctx || n_queries < 1 || !q_off || !tables || !graphs || !out) {
     set_error("gj_batch_create: bad argument");
     return GJ_E_INVALID;
@@ -91,17 +94,31 @@ gj_status gj_batch_create(gj_ctx* ctx, int32_t n_queries, const int32_t* q_off, 
   return GJ_OK;
 }
 
+// Work launched on a stream other than the context's: the context's stream
+// (on which results, views and downloads are read) waits for its end.
+static gj_status join_context_stream(gj_batch* b, hipStream_t s) {
+  if (s == b->ctx->stream) return GJ_OK;
+  gj_status st;
+  if (!b->done && (st = check(hipEventCreateWithFlags(&b->done, hipEventDisableTiming), "event"))) return st;
+  if ((st = check(hipEventRecord(b->done, s), "event record"))) return st;
+  return check(hipStreamWaitEvent(b->ctx->stream, b->done, 0), "stream wait");
+}
+
 gj_status gj_batch_launch(gj_batch* b, void* hip_stream) {
+  GJ_SCOPE(b ? b->ctx : nullptr);
   if (!b) {
     set_error("gj_batch_launch: null batch");
     return GJ_E_INVALID;
   }
   b->counters_valid = false;
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : b->ctx->stream;
-  return check(hipGraphLaunch(b->exec, s), "graph launch");
+  gj_status st = check(hipGraphLaunch(b->exec, s), "graph launch");
+  if (st) return st;
+  return join_context_stream(b, s);
 }
 
 gj_status gj_batch_launch_eager(gj_batch* b, void* hip_stream) {
+  GJ_SCOPE(b ? b->ctx : nullptr);
   if (!b) {
     set_error("gj_batch_launch_eager: null batch");
     return GJ_E_INVALID;
@@ -110,13 +127,16 @@ gj_status gj_batch_launch_eager(gj_batch* b, void* hip_stream) {
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : b->ctx->stream;
   launch_factors(b->f->plan, b->f->F, s);
   launch_summary(b->f->plan, b->f->F, b->s->S, s);
-  return check(hipGetLastError(), "batch kernels");
+  gj_status st = check(hipGetLastError(), "batch kernels");
+  if (st) return st;
+  return join_context_stream(b, s);
 }
 
 const int64_t* gj_batch_join_sizes(const gj_batch* b) { return b ? b->s->S.qsize : nullptr; }
 const int32_t* gj_batch_status(const gj_batch* b) { return b ? b->s->S.qstatus : nullptr; }
 
 gj_status gj_batch_summary(gj_batch* b, int32_t q, const gj_summary** out) {
+  GJ_SCOPE(b ? b->ctx : nullptr);
   if (!b || !out || q < 0 || q >= b->f->plan.nq) {
     set_error("gj_batch_summary: bad argument");
     return GJ_E_INVALID;

@@ -54,6 +54,7 @@ extern "C" {
 
 gj_status gj_summarize_cyclic(gj_ctx* ctx, const gj_table* tables, const gj_natural_query* q, gj_summary** out,
                               int64_t* join_size) {
+  GJ_SCOPE(ctx);
   if (!ctx || !tables || !q || !out) {
     set_error("gj_summarize_cyclic: null argument");
     return GJ_E_INVALID;

@@ -446,6 +446,22 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_group_index(const WorkItem* __rest
   }
 }
 
+// Entry frequencies as int64 (the factor view's count column).
+__global__ void __launch_bounds__(GJ_BLOCK) k_entry_counts(const WorkItem* __restrict__ wl,
+                                                           const TDesc* __restrict__ D, FPtrs F,
+                                                           int64_t* __restrict__ out) {
+  const WorkItem w = wl[blockIdx.x];
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+    if (e >= M) break;
+    const int64_t se = d.off + e;
+    out[se] = F.ecnt ? F.ecnt[se] : (int64_t)(F.eend[se] - F.estart[se]);
+  }
+}
+
 // One block per table: exclusive scan (in place) of the table's tile
 // aggregates, each a pair of 32-bit counts packed in a uint64 (no carry can
 // cross the halves: counts are < 2^31); the totals go to cnt[t][ca], cnt[t][cb].
@@ -537,6 +553,10 @@ void runs_write(hipStream_t s, int wide, const WorkItem* wl, int nwl, const TDes
 
 void group_index(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F) {
   if (nwl > 0) hipLaunchKernelGGL(k_group_index, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F);
+}
+
+void entry_counts(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F, int64_t* out) {
+  if (nwl > 0) hipLaunchKernelGGL(k_entry_counts, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, out);
 }
 
 void tile_scan_pair(hipStream_t s, const int32_t* tabs, int ntab, const TDesc* D, uint64_t* agg, int64_t* cnt, int ca,

@@ -123,6 +123,7 @@ __global__ void k_lengths(const int64_t* __restrict__ heads, int64_t* __restrict
 
 extern "C" gj_status gj_unroll_gfjs(gj_ctx* ctx, const gj_summary* s, int64_t first_row, int64_t n_rows,
                                     int32_t* const* values, int64_t* const* freqs, int64_t* n_runs) {
+  GJ_SCOPE(ctx);
   if (!ctx || !s || !values || !freqs || !n_runs || first_row < 0 || n_rows < 0) {
     set_error("gj_unroll_gfjs: bad argument");
     return GJ_E_INVALID;
@@ -131,6 +132,7 @@ extern "C" gj_status gj_unroll_gfjs(gj_ctx* ctx, const gj_summary* s, int64_t fi
     set_error("gj_unroll_gfjs: the summary has no row ids (projected, or loaded without rows)");
     return GJ_E_INVALID;
   }
+  if (gj_status st = summary_host(s)) return st;
   if (first_row > s->join_size) {
     set_error("first_row beyond the join size");
     return GJ_E_RANGE;

@@ -22,6 +22,8 @@ void tile_scan_pair(hipStream_t s, const int32_t* tabs, int ntab, const TDesc* D
 
 // separator value -> group for tables with a dense index (after the runs)
 void group_index(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F);
+// out[entry slot] = the entry's frequency (given count, or its row count)
+void entry_counts(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F, int64_t* out);
 
 // summary.hip
 void fill_i64(hipStream_t s, int64_t* p, int64_t n, int64_t v);
@@ -30,9 +32,22 @@ void up_pass(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, in
 void down_pass(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F, const SPtrs& S);
 void compact(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,
              const FPtrs& F, const SPtrs& S);
+// copies one query's join size and status (device) to caller arrays
+void export_status(hipStream_t s, const int64_t* qsize, const int32_t* qstatus, int64_t* out_size,
+                   int32_t* out_status);
 
 // desum.hip
 struct DesumArgs;
+// Launch shape of the expansion kernel (host only): staging round KS, tuples
+// per lane, grid, LDS allocated per block and used by the actual columns,
+// bytes a lane stages per round.  ok = 0 if the arguments or the shape are
+// outside what the kernel supports.
+struct DesumPlan {
+  int ok;
+  int stage, tuples_per_lane, kernel_tables, seg_bytes;
+  int64_t blocks, lds_bytes, lds_used;
+};
+DesumPlan desum_plan(int n_tables, int rowid_bytes, int n_cols, int64_t n_rows, int rounds_per_lane, int stage);
 // returns -1 if the launch does not fit one grid
 int desummarize(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables, int rounds_per_lane, int stage);
 // value columns (desum_values.hip): tuples per staging round, and the launch

@@ -470,6 +470,7 @@ gj_status sorted_factors(gj_ctx* ctx, int n, const gj_table* tables, const gj_na
 extern "C" {
 
 gj_status gj_potential_join(gj_ctx* ctx, const gj_table* tables, const gj_natural_query* q, gj_potential** out) {
+  GJ_SCOPE(ctx);
   if (!ctx || !tables || !q || !out || !q->n_keys || !q->attr || q->n_tables < 1 ||
       q->n_tables > GJ_MAX_CLIQUE_TABLES) {
     set_error("gj_potential_join: bad argument (1..%d tables)", GJ_MAX_CLIQUE_TABLES);
@@ -496,6 +497,7 @@ gj_status gj_potential_join(gj_ctx* ctx, const gj_table* tables, const gj_natura
 }
 
 gj_status gj_potential_table(const gj_potential* p, gj_potential_view* v) {
+  GJ_SCOPE(p ? p->ctx : nullptr);
   if (!p || !v) {
     set_error("gj_potential_table: null argument");
     return GJ_E_INVALID;

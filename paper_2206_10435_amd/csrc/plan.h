@@ -13,11 +13,23 @@ struct gj_ctx {
   gj_free_fn free_fn = nullptr;
   void* user = nullptr;
   gj_tune tune{};
+  std::string err;  // message of the last failed call made with this context
 };
 
 namespace gjh {
 
+// Records a failure message: on the calling thread, and on the context of the
+// entry point running on this thread (if it has one, see CtxScope).
 void set_error(const char* fmt, ...);
+
+// Names the context of the entry point running on this thread for as long as
+// the scope lives, so that set_error records on it.
+struct CtxScope {
+  gj_ctx* prev;
+  explicit CtxScope(const gj_ctx* c);
+  ~CtxScope();
+};
+#define GJ_SCOPE(c) gjh::CtxScope gj_scope_((c))
 
 // A device allocation made through the context's allocator.
 struct Buf {
@@ -110,6 +122,10 @@ gj_status sorted_factors(gj_ctx* ctx, int n, const gj_table* tables, const gj_na
                          std::vector<int32_t>& vars, std::vector<std::vector<int>>& tvar, gj_factors** out);
 // Host copy of the plan's device counters (synchronizes the stream).
 gj_status read_counters(const Plan& P, const FPtrs& F, hipStream_t s, std::vector<int64_t>& out);
+// Makes a summary's host-side state (entry counts, join size) current: reads
+// it with one synchronization if it was computed without a read-back.
+// GJ_E_OVERFLOW if the summary's query overflowed.
+gj_status summary_host(const gj_summary* s);
 
 gj_status check(hipError_t e, const char* what);
 
@@ -121,6 +137,7 @@ struct gj_factors {
   gjh::Arena arena;
   FPtrs F{};
   std::vector<int64_t> cnt_host;  // host copy of the counters
+  int64_t* ecount = nullptr;       // per entry slot: frequency (filled on the first view)
   int refs = 1;
   explicit gj_factors(gj_ctx* c) : ctx(c), arena(c) {}
 };
@@ -134,6 +151,10 @@ struct gj_summary {
   bool borrowed = false;  // part of a batch: not freed by gj_free_summary
   std::vector<int64_t> cnt_host;
   int64_t join_size = 0;
+  // computed without reading anything back (gj_summarize_batch): cnt_host,
+  // join_size and status are read on first use (gjh::summary_host)
+  bool host_stale = false;
+  int32_t status = GJ_OK;
   bool projected = false;  // entries over output attributes only: no row ids
   // result columns (table, key column) and their attribute ids when they are
   // not "the root's columns, then every other table's non-separator columns"

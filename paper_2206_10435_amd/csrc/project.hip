@@ -138,6 +138,7 @@ extern "C" {
 
 gj_status gj_summarize_projected(gj_ctx* ctx, const gj_factors* fc, const uint32_t* out_cols, gj_summary** out,
                                  int64_t* join_size) {
+  GJ_SCOPE(ctx);
   if (!ctx || !fc || !out_cols || !out) {
     set_error("gj_summarize_projected: null argument");
     return GJ_E_INVALID;
@@ -304,6 +305,7 @@ int32_t gj_summary_n_tables(const gj_summary* s) {
 
 gj_status gj_desummarize_projected(gj_ctx* ctx, const gj_summary* s, int64_t first_row, int64_t n_rows, int32_t* out,
                                    int64_t* n_written) {
+  GJ_SCOPE(ctx);
   if (!ctx || !s || n_rows < 0 || first_row < 0) {
     set_error("gj_desummarize_projected: bad argument");
     return GJ_E_INVALID;

@@ -106,6 +106,7 @@ extern "C" {
 
 gj_status gj_summary_save(gj_ctx* ctx, const gj_summary* s, const char* path, int32_t with_rows,
                           int64_t* bytes_written) {
+  GJ_SCOPE(ctx);
   if (!ctx || !s || !path) {
     set_error("gj_summary_save: null argument");
     return GJ_E_INVALID;
@@ -118,6 +119,7 @@ gj_status gj_summary_save(gj_ctx* ctx, const gj_summary* s, const char* path, in
     set_error("gj_summary_save: this summary was loaded without its rows");
     return GJ_E_INVALID;
   }
+  if (gj_status st = summary_host(s)) return st;
   const Plan& P = s->f->plan;
   const int base = P.qfirst[s->query];
   const int n = P.qfirst[s->query + 1] - base;
@@ -173,6 +175,7 @@ gj_status gj_summary_save(gj_ctx* ctx, const gj_summary* s, const char* path, in
 }
 
 gj_status gj_summary_load(gj_ctx* ctx, const char* path, gj_summary** out) {
+  GJ_SCOPE(ctx);
   if (!ctx || !path || !out) {
     set_error("gj_summary_load: null argument");
     return GJ_E_INVALID;

@@ -384,9 +384,22 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_compact_links(const WorkItem* __re
   }
 }
 
+__global__ void k_export_status(const int64_t* __restrict__ qsize, const int32_t* __restrict__ qstatus,
+                                int64_t* __restrict__ out_size, int32_t* __restrict__ out_status) {
+  if (threadIdx.x == 0) {
+    *out_size = *qsize;
+    *out_status = *qstatus;
+  }
+}
+
 }  // namespace
 
 namespace gjk {
+
+void export_status(hipStream_t s, const int64_t* qsize, const int32_t* qstatus, int64_t* out_size,
+                   int32_t* out_status) {
+  hipLaunchKernelGGL(k_export_status, dim3(1), dim3(64), 0, s, qsize, qstatus, out_size, out_status);
+}
 
 void fill_i64(hipStream_t s, int64_t* p, int64_t n, int64_t v) {
   if (n <= 0) return;

@@ -295,6 +295,7 @@ extern "C" {
 
 gj_status gj_weighted_forward(gj_ctx* ctx, const gj_factors* fc, const void* const* w, int32_t w_dtype, double* d_W,
                               gj_wstate** saved) {
+  GJ_SCOPE(ctx);
   if (!ctx || !fc || !w || !d_W || !saved || (w_dtype != 0 && w_dtype != 1)) {
     set_error("gj_weighted_forward: bad argument");
     return GJ_E_INVALID;
@@ -348,6 +349,7 @@ gj_status gj_weighted_forward(gj_ctx* ctx, const gj_factors* fc, const void* con
 }
 
 gj_status gj_weighted_backward(gj_ctx* ctx, const gj_wstate* stc, const double* d_gradW, void* const* grad_w) {
+  GJ_SCOPE(ctx);
   if (!ctx || !stc || !d_gradW || !grad_w) {
     set_error("gj_weighted_backward: bad argument");
     return GJ_E_INVALID;

@@ -39,8 +39,8 @@ class _Graph(C.Structure):
 
 class _FactorView(C.Structure):
     _fields_ = [("n_entries", C.c_int64), ("n_rows", C.c_int64), ("n_keys", C.c_int32),
-                ("keys", C.c_void_p * MAX_KEYS), ("start", C.c_void_p), ("end", C.c_void_p),
-                ("perm", C.c_void_p)]
+                ("keys", C.c_void_p * MAX_KEYS), ("count", C.c_void_p), ("start", C.c_void_p),
+                ("end", C.c_void_p), ("perm", C.c_void_p)]
 
 
 class _SummaryView(C.Structure):
@@ -74,6 +74,12 @@ class Tune(C.Structure):
                 ("desum_stage", C.c_int32)]
 
 
+class DesumLaunch(C.Structure):
+    _fields_ = [("stage", C.c_int32), ("tuples_per_lane", C.c_int32), ("kernel_tables", C.c_int32),
+                ("change_bits", C.c_int32), ("seg_bytes", C.c_int32), ("blocks", C.c_int64),
+                ("lds_bytes", C.c_int64), ("lds_used", C.c_int64)]
+
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
@@ -84,12 +90,13 @@ _vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
 SIGNATURES = {
     "gj_ctx_create": (C.c_int, [C.c_int, _vp, ALLOC_FN, FREE_FN, _vp, _vp]),
     "gj_ctx_destroy": (None, [_vp]),
-    "gj_last_error": (C.c_char_p, []),
+    "gj_last_error": (C.c_char_p, [_vp]),
     "gj_validate": (C.c_int, [_vp, _vp]),
     "gj_build_factors": (C.c_int, [_vp, _vp, _vp, _vp]),
     "gj_factor_table": (C.c_int, [_vp, _i32, _vp]),
     "gj_free_factors": (None, [_vp]),
     "gj_summarize": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "gj_summarize_batch": (C.c_int, [_vp, _vp, _i32, _vp, _vp, _vp]),
     "gj_summary_table": (C.c_int, [_vp, _i32, _vp]),
     "gj_summary_edge": (C.c_int, [_vp, _i32, _vp]),
     "gj_summary_join_size": (_i64, [_vp]),
@@ -109,6 +116,7 @@ SIGNATURES = {
     "gj_free_batch": (None, [_vp]),
     "gj_download": (C.c_int, [_vp, _vp, _vp, _sz]),
     "gj_ctx_set_tune": (C.c_int, [_vp, _vp]),
+    "gj_desum_launch_config": (C.c_int, [_i32, _i32, _i32, _i64, _vp, _vp]),
     "gj_colset_create": (C.c_int, [_vp, _vp, _i32, _vp, _vp, _vp]),
     "gj_free_colset": (None, [_vp]),
     "gj_desummarize_values": (C.c_int, [_vp, _vp, _vp, _i64, _i64, _vp, _vp]),
@@ -142,9 +150,11 @@ def load_library(path: str = LIB_PATH):
     return L
 
 
-def _check(rc: int):
+def _check(rc: int, ctx_h=None):
+    """Raise GJError with the message the library recorded for context `ctx_h`
+    (None: for the calling thread, the calls that take no context)."""
     if rc != GJ_OK:
-        raise GJError(rc, load_library().gj_last_error().decode())
+        raise GJError(rc, load_library().gj_last_error(ctx_h).decode())
 
 
 def _graph_struct(parent, sep_col, parent_col):
@@ -164,6 +174,16 @@ def validate(n_rows: Sequence[int], n_keys: Sequence[int], parent, sep_col, pare
         tabs[t] = _Table(int(n), int(k), C.cast(fake, C.c_void_p))
     g, arrs = _graph_struct(parent, sep_col, parent_col)
     _check(L.gj_validate(tabs, C.byref(g)))
+
+
+def desum_launch_config(n_tables: int, rowid_bytes: int, n_cols: int, n_rows: int,
+                        tune: Optional[Tune] = None) -> dict:
+    """Launch shape of the expansion kernel for these arguments (host only)."""
+    L = load_library()
+    out = DesumLaunch()
+    _check(L.gj_desum_launch_config(int(n_tables), int(rowid_bytes), int(n_cols), int(n_rows),
+                                    C.byref(tune) if tune is not None else None, C.byref(out)))
+    return {k: int(getattr(out, k)) for k, _ in DesumLaunch._fields_}
 
 
 def _natural_struct(attrs):
@@ -228,6 +248,9 @@ class Context:
         _check(self.L.gj_ctx_create(device, C.c_void_p(sptr), self._alloc_cb, self._free_cb, None, C.byref(h)))
         self.h = h
 
+    def _check(self, rc: int):
+        _check(rc, self.h)
+
     def close(self):
         if getattr(self, "h", None):
             self.L.gj_ctx_destroy(self.h)
@@ -235,12 +258,12 @@ class Context:
 
     def set_tune(self, sort_items=8, radix_bits=8, desum_rounds=0, desum_stage=4):
         t = Tune(sort_items, radix_bits, desum_rounds, desum_stage)
-        _check(self.L.gj_ctx_set_tune(self.h, C.byref(t)))
+        self._check(self.L.gj_ctx_set_tune(self.h, C.byref(t)))
 
     def download(self, ptr: int, n: int, dtype) -> np.ndarray:
         out = np.empty(max(n, 0), dtype=dtype)
         if n > 0:
-            _check(self.L.gj_download(self.h, out.ctypes.data_as(C.c_void_p), C.c_void_p(ptr), out.nbytes))
+            self._check(self.L.gj_download(self.h, out.ctypes.data_as(C.c_void_p), C.c_void_p(ptr), out.nbytes))
         return out
 
     # -- stage 1 ------------------------------------------------------------
@@ -248,15 +271,37 @@ class Context:
         tabs, keep = _tables_struct(tables)
         g, arrs = _graph_struct(parent, sep_col, parent_col)
         h = C.c_void_p()
-        _check(self.L.gj_build_factors(self.h, tabs, C.byref(g), C.byref(h)))
+        self._check(self.L.gj_build_factors(self.h, tabs, C.byref(g), C.byref(h)))
         return Factors(self, h, len(tables))
 
     # -- stage 2 ------------------------------------------------------------
     def summarize(self, f: "Factors") -> "Summary":
         h = C.c_void_p()
         q = C.c_int64()
-        _check(self.L.gj_summarize(self.h, f.h, C.byref(h), C.byref(q)))
+        self._check(self.L.gj_summarize(self.h, f.h, C.byref(h), C.byref(q)))
         return Summary(self, h, f.n_tables, int(q.value))
+
+    def summarize_batch(self, factors: List["Factors"], d_join_sizes, d_status,
+                        outs: Optional[List["Summary"]] = None) -> List["Summary"]:
+        """Summaries of several factor sets without reading anything back:
+        join sizes / statuses go to the int64 / int32 device tensors given.
+        Passing the summaries of an earlier call recomputes them in place
+        (nothing allocated: capturable in a HIP graph)."""
+        import torch
+
+        n = len(factors)
+        if d_join_sizes.dtype != torch.int64 or d_status.dtype != torch.int32 or \
+                d_join_sizes.numel() < n or d_status.numel() < n:
+            raise ValueError("need int64 join-size and int32 status device tensors of n_queries entries")
+        fp = (C.c_void_p * max(n, 1))(*[f.h for f in factors])
+        op = (C.c_void_p * max(n, 1))(*([s.h for s in outs] if outs is not None else [None] * n))
+        self._check(self.L.gj_summarize_batch(self.h, fp, n, op, C.c_void_p(d_join_sizes.data_ptr()),
+                                              C.c_void_p(d_status.data_ptr())))
+        if outs is not None:
+            for s in outs:
+                s.refresh()
+            return outs
+        return [Summary(self, C.c_void_p(op[i]), f.n_tables, None) for i, f in enumerate(factors)]
 
     def summarize_projected(self, f: "Factors", out_cols) -> "Summary":
         """Early projection: out_cols[t] has bit c set for every output key
@@ -266,18 +311,18 @@ class Context:
             raise ValueError("one mask word per table")
         h = C.c_void_p()
         q = C.c_int64()
-        _check(self.L.gj_summarize_projected(self.h, f.h, m.ctypes.data_as(C.c_void_p), C.byref(h), C.byref(q)))
+        self._check(self.L.gj_summarize_projected(self.h, f.h, m.ctypes.data_as(C.c_void_p), C.byref(h), C.byref(q)))
         return Summary(self, h, int(self.L.gj_summary_n_tables(h)), int(q.value), projected=True)
 
     def save(self, s: "Summary", path: str, with_rows: bool = True) -> int:
         """Writes the summary to `path`; returns the file size in bytes."""
         nb = C.c_int64()
-        _check(self.L.gj_summary_save(self.h, s.h, os.fsencode(path), 1 if with_rows else 0, C.byref(nb)))
+        self._check(self.L.gj_summary_save(self.h, s.h, os.fsencode(path), 1 if with_rows else 0, C.byref(nb)))
         return int(nb.value)
 
     def load(self, path: str) -> "Summary":
         h = C.c_void_p()
-        _check(self.L.gj_summary_load(self.h, os.fsencode(path), C.byref(h)))
+        self._check(self.L.gj_summary_load(self.h, os.fsencode(path), C.byref(h)))
         js = int(self.L.gj_summary_join_size(h))
         return Summary(self, h, int(self.L.gj_summary_n_tables(h)), js)
 
@@ -295,7 +340,7 @@ class Context:
         if out.numel() < n_rows * nc:
             raise ValueError("out is too small")
         nw = C.c_int64()
-        _check(self.L.gj_desummarize_projected(self.h, s.h, int(first_row), int(n_rows),
+        self._check(self.L.gj_desummarize_projected(self.h, s.h, int(first_row), int(n_rows),
                                                C.c_void_p(out.data_ptr()), C.byref(nw)))
         return int(nw.value)
 
@@ -306,10 +351,10 @@ class Context:
         tabs, keep = _tables_struct(tables)
         q, keep2 = _natural_struct(attrs)
         h = C.c_void_p()
-        _check(self.L.gj_potential_join(self.h, tabs, C.byref(q), C.byref(h)))
+        self._check(self.L.gj_potential_join(self.h, tabs, C.byref(q), C.byref(h)))
         try:
             v = _PotView()
-            _check(self.L.gj_potential_table(h, C.byref(v)))
+            self._check(self.L.gj_potential_table(h, C.byref(v)))
             n, nv = int(v.n_entries), int(v.n_vars)
             keys = (np.stack([self.download(v.keys[i], n, np.int32) for i in range(nv)], axis=1)
                     if nv else np.zeros((n, 0), np.int32))
@@ -326,7 +371,7 @@ class Context:
         q, keep2 = _natural_struct(attrs)
         h = C.c_void_p()
         js = C.c_int64()
-        _check(self.L.gj_summarize_cyclic(self.h, tabs, C.byref(q), C.byref(h), C.byref(js)))
+        self._check(self.L.gj_summarize_cyclic(self.h, tabs, C.byref(q), C.byref(h), C.byref(js)))
         return Summary(self, h, int(self.L.gj_summary_n_tables(h)), int(js.value), projected=True)
 
     def result_attributes(self, s: "Summary"):
@@ -343,7 +388,7 @@ class Context:
         if out.numel() < n_rows * s.n_tables:
             raise ValueError("out is too small")
         nw = C.c_int64()
-        _check(self.L.gj_desummarize(self.h, s.h, int(first_row), int(n_rows), out.element_size(),
+        self._check(self.L.gj_desummarize(self.h, s.h, int(first_row), int(n_rows), out.element_size(),
                                      C.c_void_p(out.data_ptr()), C.byref(nw)))
         return int(nw.value)
 
@@ -356,7 +401,7 @@ class Context:
                 raise ValueError("value columns must be contiguous int32 device tensors")
         ptrs = (C.c_void_p * len(columns))(*[c.data_ptr() for _, c in columns])
         h = C.c_void_p()
-        _check(self.L.gj_colset_create(self.h, s.h, len(columns), tabs.ctypes.data_as(C.c_void_p), ptrs,
+        self._check(self.L.gj_colset_create(self.h, s.h, len(columns), tabs.ctypes.data_as(C.c_void_p), ptrs,
                                        C.byref(h)))
         return ColSet(self, h, len(columns))
 
@@ -370,7 +415,7 @@ class Context:
         if out.numel() < n_rows * cs.n_cols:
             raise ValueError("out is too small")
         nw = C.c_int64()
-        _check(self.L.gj_desummarize_values(self.h, s.h, cs.h, int(first_row), int(n_rows),
+        self._check(self.L.gj_desummarize_values(self.h, s.h, cs.h, int(first_row), int(n_rows),
                                             C.c_void_p(out.data_ptr()), C.byref(nw)))
         return int(nw.value)
 
@@ -384,7 +429,7 @@ class Context:
         vp = (C.c_void_p * L)(*[v.data_ptr() for v in vals])
         fp = (C.c_void_p * L)(*[f.data_ptr() for f in frqs])
         nr = (C.c_int64 * L)()
-        _check(self.L.gj_unroll_gfjs(self.h, s.h, int(first_row), int(n_rows), vp, fp, nr))
+        self._check(self.L.gj_unroll_gfjs(self.h, s.h, int(first_row), int(n_rows), vp, fp, nr))
         return [(vals[i][: nr[i]].cpu().numpy(), frqs[i][: nr[i]].cpu().numpy()) for i in range(L)]
 
     # -- weighted ------------------------------------------------------------
@@ -397,13 +442,13 @@ class Context:
         wp = (C.c_void_p * len(weights))(*[w.data_ptr() for w in weights])
         W = torch.empty((), dtype=torch.float64, device=f"cuda:{self.device}")
         st = C.c_void_p()
-        _check(self.L.gj_weighted_forward(self.h, f.h, wp, 1 if dt == torch.float64 else 0,
+        self._check(self.L.gj_weighted_forward(self.h, f.h, wp, 1 if dt == torch.float64 else 0,
                                           C.c_void_p(W.data_ptr()), C.byref(st)))
         return W, WState(self, st)
 
     def weighted_backward(self, st: "WState", gradW, grads: List["torch.Tensor"]):
         gp = (C.c_void_p * len(grads))(*[g.data_ptr() for g in grads])
-        _check(self.L.gj_weighted_backward(self.h, st.h, C.c_void_p(gradW.data_ptr()), gp))
+        self._check(self.L.gj_weighted_backward(self.h, st.h, C.c_void_p(gradW.data_ptr()), gp))
 
     # -- batch ---------------------------------------------------------------
     def batch_create(self, queries: List[dict], tune: Optional[Tune] = None) -> "Batch":
@@ -421,7 +466,7 @@ class Context:
         tabs, keep2 = _tables_struct(tabs_all)
         qo = np.array(qoff, dtype=np.int32)
         h = C.c_void_p()
-        _check(self.L.gj_batch_create(self.h, len(queries), qo.ctypes.data_as(C.c_void_p), tabs, graphs,
+        self._check(self.L.gj_batch_create(self.h, len(queries), qo.ctypes.data_as(C.c_void_p), tabs, graphs,
                                       C.byref(tune) if tune is not None else None, C.byref(h)))
         return Batch(self, h, [len(q["tables"]) for q in queries], keep=(keep, keep2, queries))
 
@@ -451,21 +496,34 @@ class Factors:
 
     def table(self, t: int) -> dict:
         v = _FactorView()
-        _check(self.ctx.L.gj_factor_table(self.h, t, C.byref(v)))
+        self.ctx._check(self.ctx.L.gj_factor_table(self.h, t, C.byref(v)))
         M, N, k = int(v.n_entries), int(v.n_rows), int(v.n_keys)
         d = self.ctx.download
         keys = np.stack([d(v.keys[c], M, np.int32) for c in range(k)], axis=1) if k else np.zeros((M, 0), np.int32)
-        start = d(v.start, M, np.int32)
-        end = d(v.end, M, np.int32)
-        return dict(keys=keys, start=start, end=end, count=(end - start).astype(np.int64),
-                    perm=d(v.perm, N, np.int32))
+        return dict(keys=keys, start=d(v.start, M, np.int32), end=d(v.end, M, np.int32),
+                    count=d(v.count, M, np.int64), perm=d(v.perm, N, np.int32))
 
 
 class Summary:
-    def __init__(self, ctx: Context, h, n_tables: int, join_size: int, borrowed: bool = False,
+    def __init__(self, ctx: Context, h, n_tables: int, join_size: Optional[int], borrowed: bool = False,
                  projected: bool = False):
-        self.ctx, self.h, self.n_tables, self.join_size, self.borrowed = ctx, h, n_tables, join_size, borrowed
+        self.ctx, self.h, self.n_tables, self._join_size, self.borrowed = ctx, h, n_tables, join_size, borrowed
         self.projected = projected
+
+    @property
+    def join_size(self) -> int:
+        """The join size (read from the device on first use for a summary made
+        by summarize_batch; GJError GJ_E_OVERFLOW if its query overflowed)."""
+        if self._join_size is None:
+            js = int(self.ctx.L.gj_summary_join_size(self.h))
+            if js < 0:
+                raise GJError(GJ_E_OVERFLOW, self.ctx.L.gj_last_error(self.ctx.h).decode())
+            self._join_size = js
+        return self._join_size
+
+    def refresh(self):
+        """Forget the cached join size (after the summary was recomputed in place)."""
+        self._join_size = None
 
     def __del__(self):
         if not self.borrowed and getattr(self, "h", None) is not None and self.ctx.h:
@@ -474,7 +532,7 @@ class Summary:
 
     def table(self, t: int) -> dict:
         v = _SummaryView()
-        _check(self.ctx.L.gj_summary_table(self.h, t, C.byref(v)))
+        self.ctx._check(self.ctx.L.gj_summary_table(self.h, t, C.byref(v)))
         M, k = int(v.n_entries), int(v.n_keys)
         d = self.ctx.download
         keys = np.stack([d(v.keys[c], M, np.int32) for c in range(k)], axis=1)
@@ -483,7 +541,7 @@ class Summary:
 
     def edge(self, t: int) -> dict:
         v = _EdgeView()
-        _check(self.ctx.L.gj_summary_edge(self.h, t, C.byref(v)))
+        self.ctx._check(self.ctx.L.gj_summary_edge(self.h, t, C.byref(v)))
         n = int(v.n)
         d = self.ctx.download
         return dict(s=d(v.s, n, np.int32), M=d(v.M, n, np.int64), D=d(v.D, n, np.int64))
@@ -521,7 +579,7 @@ class Batch:
     def launch(self, graph: bool = True, stream=None):
         sp = C.c_void_p(stream.cuda_stream) if stream is not None else None
         fn = self.ctx.L.gj_batch_launch if graph else self.ctx.L.gj_batch_launch_eager
-        _check(fn(self.h, sp))
+        self.ctx._check(fn(self.h, sp))
 
     def results(self):
         nq = len(self.n_tables)
@@ -531,7 +589,7 @@ class Batch:
 
     def summary(self, q: int) -> Summary:
         h = C.c_void_p()
-        _check(self.ctx.L.gj_batch_summary(self.h, q, C.byref(h)))
+        self.ctx._check(self.ctx.L.gj_batch_summary(self.h, q, C.byref(h)))
         js = int(self.ctx.L.gj_summary_join_size(h))
         return Summary(self.ctx, h, self.n_tables[q], js, borrowed=True)
 

@@ -13,10 +13,10 @@
   subtree -- each counted separately, by brute force over the join result.
 
 A mutation test plants plausible mistakes in scratch copies of the oracle
-source (separator not first, rows descending inside an entry, starts that are
-entry indexes, transposed key columns, deleted completions moved into U, a
-deleted child's outside message taken for its subtree's) and checks that these pins catch
-every one of them.
+source (separator not first, rows descending inside an entry, starts that
+are entry indexes, key columns written in sort order instead of declared
+order, deleted completions moved into U, a deleted child's outside message
+taken for its subtree's) and checks that these pins catch every one of them.
 """
 import collections
 import concurrent.futures as cf
@@ -212,12 +212,12 @@ MUTANTS = {
         "      if (t == 0 || c != sep[t]) v.push_back(c);\n    return v;",
         "    for (int c = 0; c < K[t]; ++c) v.push_back(c);\n    return v;")],
     "rows_descending": [(
-        "  for (int64_t r = 0; r < s.N[t]; ++r) g[s.canon_key(t, r)].push_back((int32_t)r);",
-        "  for (int64_t r = s.N[t] - 1; r >= 0; --r) g[s.canon_key(t, r)].push_back((int32_t)r);")],
-    "starts_are_indexes": [("if (start) start[e] = pos;", "if (start) start[e] = e;")],
-    "keys_transposed": [(
-        "keys[e * s.K[t] + cc[i]] = kv.first[i];\n    if (cnt) cnt[e]",
-        "keys[e * s.K[t] + i] = kv.first[i];\n    if (cnt) cnt[e]")],
+        "return less_key(a, b) || (!less_key(b, a) && a < b);",
+        "return less_key(a, b) || (!less_key(b, a) && a > b);")],
+    "starts_are_indexes": [("if (start) start[e] = g.start[e];", "if (start) start[e] = e;")],
+    "keys_in_sort_order": [(
+        "      for (int c = 0; c < s.K[t]; ++c) keys[e * s.K[t] + c] = s.key(t, c, r0);",
+        "      for (int c = 0; c < s.K[t]; ++c) keys[e * s.K[t] + c] = s.key(t, s.canon_cols(t)[c], r0);")],
     "deleted_weight_in_U": [
         ("      if (!kept[ch]) w = smul(w, lookup(s.sumdown[ch], s.key(t, s.pcol[ch], r)));",
          "      if (false) w = smul(w, lookup(s.sumdown[ch], s.key(t, s.pcol[ch], r)));"),
@@ -227,7 +227,7 @@ MUTANTS = {
         "if (!kept[ch]) w = smul(w, lookup(s.upval[ch], s.key(t, s.pcol[ch], r)));")],
 }
 
-FACTOR_MUTANTS = ("separator_not_first", "rows_descending", "starts_are_indexes", "keys_transposed")
+FACTOR_MUTANTS = ("separator_not_first", "rows_descending", "starts_are_indexes", "keys_in_sort_order")
 SPLIT_MUTANTS = ("deleted_weight_in_U", "deleted_child_wrong_message")
 
 
