@@ -397,6 +397,7 @@ gj_status gj_weighted_forward(gj_ctx* ctx, const gj_factors* f, const void* cons
 gj_status gj_weighted_backward(gj_ctx* ctx, const gj_wstate* st, const double* d_gradW, void* const* grad_w);
 void gj_free_wstate(gj_wstate* st);
 
+
 /* ---- batched queries ----
  * Plans n_queries independent queries (tables of query q are
  * tables[q_off[q] .. q_off[q+1]), graphs[q] its join tree): reads the key

@@ -279,7 +279,10 @@ typedef std::map<std::vector<int32_t>, std::vector<int32_t>> Groups;
 const Groups& candidates(State& s, int t, const std::vector<int32_t>& rep, Groups& scratch) {
   if (t == 0) {
     if (!s.root_grouped) {
-      s.root_groups = group_by(s, 0);
+      const SortedGroups g = sorted_groups(s, 0);
+      for (size_t x = 0; x + 1 < g.start.size(); ++x)
+        s.root_groups.emplace_hint(s.root_groups.end(), s.canon_key(0, g.rows[g.start[x]]),
+                                   std::vector<int32_t>(g.rows.begin() + g.start[x], g.rows.begin() + g.start[x + 1]));
       s.root_grouped = true;
     }
     return s.root_groups;
@@ -435,6 +438,55 @@ void orc_sort_canonical(void* h, int32_t* tuples, int64_t count) {
   std::vector<int32_t> tmp(tuples, tuples + count * n);
   for (int64_t i = 0; i < count; ++i)
     for (int t = 0; t < n; ++t) tuples[i * n + t] = tmp[idx[i] * n + t];
+}
+
+// Checks result tuples (row-major, count x n row ids, int64) against the
+// definition of the sorted result: every row id is a row of its table, every
+// tuple agrees on every join edge (Sec. 1.1), and every tuple comes strictly
+// after the one before it in the result order (attribute values in
+// result-column order, then the row ids; Definition 1).  The tuples are split
+// over `threads` threads.  Returns -1 if all pass, else the index of the first
+// tuple that fails.
+int64_t orc_check_tuples(void* h, const int64_t* tuples, int64_t count, int threads) {
+  State& s = *(State*)h;
+  const int n = s.n;
+  std::vector<std::pair<int, int>> cols;  // (table, column) of every result column
+  for (int t = 0; t < n; ++t)
+    for (int c : s.sigma_cols(t)) cols.push_back({t, c});
+  auto valid = [&](const int64_t* r) {
+    for (int t = 0; t < n; ++t)
+      if (r[t] < 0 || r[t] >= s.N[t]) return false;
+    for (int t = 1; t < n; ++t)
+      if (s.key(t, s.sep[t], r[t]) != s.key(s.par[t], s.pcol[t], r[s.par[t]])) return false;
+    return true;
+  };
+  auto before = [&](const int64_t* a, const int64_t* b) {  // a strictly before b
+    for (auto& tc : cols) {
+      const int32_t x = s.key(tc.first, tc.second, a[tc.first]), y = s.key(tc.first, tc.second, b[tc.first]);
+      if (x != y) return x < y;
+    }
+    for (int t = 0; t < n; ++t)
+      if (a[t] != b[t]) return a[t] < b[t];
+    return false;
+  };
+  if (threads < 1) threads = 1;
+  std::vector<int64_t> first_bad(threads, -1);
+  auto work = [&](int id) {
+    const int64_t lo = count * id / threads, hi = count * (id + 1) / threads;
+    for (int64_t i = lo; i < hi; ++i) {
+      const int64_t* r = tuples + i * n;
+      if (!valid(r) || (i > 0 && !before(r - n, r))) {
+        first_bad[id] = i;
+        return;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int i = 0; i < threads; ++i) th.emplace_back(work, i);
+  for (auto& x : th) x.join();
+  for (int64_t b : first_bad)
+    if (b >= 0) return b;
+  return -1;
 }
 
 // Value of result column `level` (attribute values in result-column order).

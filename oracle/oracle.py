@@ -76,6 +76,8 @@ def _declare(L):
     L.orc_projection.restype = C.c_int
     L.orc_projected_table.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp]
     L.orc_projected_table.restype = i64
+    L.orc_check_tuples.argtypes = [vp, vp, i64, C.c_int]
+    L.orc_check_tuples.restype = i64
     L.orc_nat_open.restype = vp
     L.orc_nat_open.argtypes = [i32, vp, vp, vp, vp]
     L.orc_nat_close.argtypes = [vp]
@@ -214,6 +216,13 @@ class Oracle:
         nr = np.zeros(L, dtype=np.int64)
         self.L.orc_gfjs(self.h, _p(st), cnt, _p(vals), _p(freqs), _p(nr))
         return [(vals[i, : nr[i]].copy(), freqs[i, : nr[i]].copy()) for i in range(L)]
+
+    def check_tuples(self, tuples, threads=8):
+        """-1 if every row-id tuple (count x n, int64) is a join tuple coming
+        strictly after its predecessor in the result order; else the index of
+        the first one that is not."""
+        t = np.ascontiguousarray(tuples, dtype=np.int64)
+        return int(self.L.orc_check_tuples(self.h, _p(t), int(t.shape[0]), int(threads)))
 
     def unrank(self, R):
         out = np.zeros(self.n, dtype=np.int32)

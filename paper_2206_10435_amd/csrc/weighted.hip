@@ -385,4 +385,5 @@ void gj_free_wstate(gj_wstate* st) {
 }
 
 
+
 }  // extern "C"

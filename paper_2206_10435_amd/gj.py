@@ -213,7 +213,9 @@ def junction_tree(attrs) -> dict:
 class Context:
     """A device, a stream and PyTorch's caching allocator."""
 
-    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True):
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True, allocator=None):
+        """`allocator`: optional (alloc(nbytes) -> device address or 0, free(address))
+        Python callables used instead of PyTorch's caching allocator."""
         import torch
 
         self.torch = torch
@@ -222,7 +224,24 @@ class Context:
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         sptr = self.stream.cuda_stream
         self._live = {}
-        if torch_allocator:
+        if allocator is not None:
+            user_alloc, user_free = allocator
+
+            def _alloc(nbytes, user):
+                try:
+                    return user_alloc(int(nbytes)) or None
+                except Exception:
+                    return None
+
+            def _free(ptr, user):
+                try:
+                    user_free(ptr)
+                except Exception:
+                    pass
+
+            self._alloc_cb = ALLOC_FN(_alloc)
+            self._free_cb = FREE_FN(_free)
+        elif torch_allocator:
             alloc_fn = torch.cuda.caching_allocator_alloc
             delete_fn = torch.cuda.caching_allocator_delete
             stream_ = self.stream

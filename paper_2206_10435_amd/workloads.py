@@ -219,26 +219,32 @@ def cfg4(seed: int = BASE_SEED, n_rows: int = 1_000_000, domain: int = 10_000, s
     return q, w64, w32
 
 
-def cfg5(seed: int = BASE_SEED, n_queries: int = 256, min_rows_exp: float = 3.0,
-         max_rows_exp: float = 6.0, min_dom_exp: float = 2.0, max_dom_exp: float = 5.0,
-         max_tables: int = 6) -> List[Query]:
-    """Many independent queries: 2..6 tables, chain or star, log-uniform sizes and domains,
-    Zipf exponent uniform in [0, 1.5]."""
-    out = []
-    for qi in range(n_queries):
-        rng = _rng(seed, 5, qi, 999)
-        n = int(rng.integers(2, max_tables + 1))
-        shape = "chain" if rng.random() < 0.5 else "star"
-        sizes = [int(round(10 ** rng.uniform(min_rows_exp, max_rows_exp))) for _ in range(n)]
-        s = float(rng.uniform(0.0, 1.5))
-        dom = int(round(10 ** rng.uniform(min_dom_exp, max_dom_exp)))
-        sub = seed * 1000 + qi
-        if shape == "chain" or n == 2:
-            q = chain_query(sub, 5, n, sizes, dom, s, name=f"q{qi}_chain{n}")
-        else:
-            q = star_query(sub, 5, n, sizes, dom, s, name=f"q{qi}_star{n}")
-        out.append(q)
-    return out
+def cfg5_query(qi: int, attempt: int = 0, seed: int = BASE_SEED, min_rows_exp: float = 3.0,
+               max_rows_exp: float = 6.0, min_dom_exp: float = 2.0, max_dom_exp: float = 5.0,
+               max_tables: int = 6) -> Query:
+    """Query qi of the many-query batch: 2..6 tables, chain or star, log-uniform
+    sizes and domains, Zipf exponent uniform in [0, 1.5].  `attempt` > 0 draws
+    a fresh query from its own streams (the batch replaces a query whose join
+    size is too large by a later attempt; which attempt is kept is decided
+    outside this module)."""
+    rng = _rng(seed, 5, qi, 999) if attempt == 0 else _rng(seed, 5, qi, 999 + 1000 * attempt)
+    n = int(rng.integers(2, max_tables + 1))
+    shape = "chain" if rng.random() < 0.5 else "star"
+    sizes = [int(round(10 ** rng.uniform(min_rows_exp, max_rows_exp))) for _ in range(n)]
+    s = float(rng.uniform(0.0, 1.5))
+    dom = int(round(10 ** rng.uniform(min_dom_exp, max_dom_exp)))
+    sub = seed * 1000 + qi + attempt * 1_000_000
+    suffix = "" if attempt == 0 else f"_a{attempt}"
+    if shape == "chain" or n == 2:
+        return chain_query(sub, 5, n, sizes, dom, s, name=f"q{qi}_chain{n}{suffix}")
+    return star_query(sub, 5, n, sizes, dom, s, name=f"q{qi}_star{n}{suffix}")
+
+
+def cfg5(seed: int = BASE_SEED, n_queries: int = 256, attempts=None, **kw) -> List[Query]:
+    """Many independent queries (see cfg5_query); attempts[qi] (default 0)
+    picks which draw of query qi is used."""
+    return [cfg5_query(qi, 0 if attempts is None else int(attempts[qi]), seed=seed, **kw)
+            for qi in range(n_queries)]
 
 
 def random_tree_query(seed: int, n_tables: int, max_rows: int, domain: int, s: float = 0.0,

@@ -373,3 +373,42 @@ def test_reroot_invariance(oracle_mod):
         for k, t in enumerate(order):
             assert np.allclose(gr[k], g0[t], rtol=1e-13, atol=0)
             assert np.array_equal(orr.fanouts(k), o.fanouts(t))
+
+
+def test_check_tuples_accepts_sorted_result_and_rejects_corruptions(oracle_mod):
+    """The chunk checker (every tuple a join tuple, strictly increasing in the
+    result order) accepts the brute-force result sorted by (values, row ids)
+    in Python, and names the first bad tuple of a swapped pair, a duplicate,
+    a row id out of range and a tuple that breaks a join edge."""
+    checked = 0
+    for q in [load_fig1()] + _tiny_queries():
+        o = oracle_mod.Oracle(q)
+        bf = o.brute_force().astype(np.int64)
+        if len(bf) < 4:
+            continue
+        n = q.n_tables
+        cols = [(t, c) for t in range(n) for c in range(len(q.tables[t])) if t == 0 or c != q.sep_col[t]]
+        key = lambda r: tuple(int(q.tables[t][c][r[t]]) for t, c in cols) + tuple(int(x) for x in r)
+        ref = np.array(sorted(bf.tolist(), key=key), dtype=np.int64)
+        for threads in (1, 3):
+            assert o.check_tuples(ref, threads) == -1
+        sw = ref.copy()
+        sw[[1, 2]] = sw[[2, 1]]
+        assert o.check_tuples(sw, 2) == 2
+        dup = ref.copy()
+        dup[3] = dup[2]
+        assert o.check_tuples(dup, 2) == 3
+        oob = ref.copy()
+        oob[1, n - 1] = q.n_rows(n - 1)
+        assert o.check_tuples(oob, 2) == 1
+        # a row of the last table whose separator value differs from the one its tuple needs
+        t = n - 1
+        if n > 1:
+            need = q.tables[q.parent[t]][q.parent_col[t]][ref[2, q.parent[t]]]
+            other = np.nonzero(q.tables[t][q.sep_col[t]] != need)[0]
+            if len(other):
+                brk = ref.copy()
+                brk[2, t] = other[0]
+                assert o.check_tuples(brk, 2) == 2
+        checked += 1
+    assert checked >= 8
