@@ -397,6 +397,21 @@ gj_status gj_weighted_forward(gj_ctx* ctx, const gj_factors* f, const void* cons
 gj_status gj_weighted_backward(gj_ctx* ctx, const gj_wstate* st, const double* d_gradW, void* const* grad_w);
 void gj_free_wstate(gj_wstate* st);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid allocation:
+ * W and every row's gradient in one call, the results of gj_weighted_forward
+ * followed by gj_weighted_backward, with no allocation and no host
+ * synchronization.  Arguments as there; d_gradW (device float64) scales the
+ * gradients, NULL meaning 1; *d_W (device) receives W and grad_w[t] (device,
+ * n_rows(t) values of w_dtype) the gradients.  The call's intermediate state
+ * (36 bytes per row and a little more) lives in one fixed device array of
+ * GJ_NOALLOC_SCRATCH_BYTES that every device running the library holds until
+ * the process ends; a query that needs more -> GJ_E_INVALID, naming the size.
+ * Every call on a device shares that array: calls that overlap on one device
+ * (other streams, other threads) race and must be ordered by the caller. */
+#define GJ_NOALLOC_SCRATCH_BYTES ((size_t)160 << 20)
+gj_status gj_weighted_grad_noalloc(gj_ctx* ctx, const gj_factors* f, const void* const* w, int32_t w_dtype,
+                                   const double* d_gradW, double* d_W, void* const* grad_w);
 
 /* ---- batched queries ----
  * Plans n_queries independent queries (tables of query q are

@@ -21,6 +21,7 @@
 // its grouped row positions; downward terms are summed per tile in an LDS
 // hash table first.  At unit weights every value is an integer below 2^53,
 // so every order of summation gives the exact integer counts.
+#include <mutex>
 #include <vector>
 
 #include "kernels.h"
@@ -384,6 +385,130 @@ void gj_free_wstate(gj_wstate* st) {
   if (f) gj_free_factors(f);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The same forward + adjoint with no allocation.  All intermediate state of
+// the call (per entry slot cw, Uw; per group slot Mw, Dw; the links; the unit
+// incoming gradient) lives in `scratch`, a fixed array every device that runs
+// the library holds until the process ends.  Host code never passes the
+// array's name to a kernel: the array's device address on each device is
+// looked up once with hipGetSymbolAddress and kept per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[GJ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on ctx's device (looked up on the first call
+// made on that device, with the device current).
+gj_status scratch_address(gj_ctx* ctx, unsigned char** out) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices) {
+    set_error("gj_weighted_grad_noalloc: device %d out of range", ctx->device);
+    return GJ_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    int cur = -1;
+    gj_status st = check(hipGetDevice(&cur), "hipGetDevice");
+    if (st) return st;
+    if (cur != ctx->device && (st = check(hipSetDevice(ctx->device), "hipSetDevice"))) return st;
+    void* p = nullptr;
+    st = check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address");
+    if (cur != ctx->device) {
+      const gj_status st2 = check(hipSetDevice(cur), "hipSetDevice");
+      if (!st) st = st2;
+    }
+    if (st) return st;
+    if (!p) {
+      set_error("gj_weighted_grad_noalloc: no device address for the scratch array");
+      return GJ_E_DEVICE;
+    }
+    g_scratch_ptr[ctx->device] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[ctx->device]);
+  return GJ_OK;
+}
+
+int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+gj_status gj_weighted_grad_noalloc(gj_ctx* ctx, const gj_factors* fc, const void* const* w, int32_t w_dtype,
+                                   const double* d_gradW, double* d_W, void* const* grad_w) {
+  GJ_SCOPE(ctx);
+  if (!ctx || !fc || !w || !d_W || !grad_w || (w_dtype != 0 && w_dtype != 1)) {
+    set_error("gj_weighted_grad_noalloc: bad argument");
+    return GJ_E_INVALID;
+  }
+  const gj_factors* f = fc;
+  const Plan& Pl = f->plan;
+  if (Pl.nq != 1) {
+    set_error("gj_weighted_grad_noalloc: factors of a single query expected");
+    return GJ_E_INVALID;
+  }
+  for (int t = 0; t < Pl.nt; ++t)
+    if (Pl.ht[t].n > 0 && (!w[t] || !grad_w[t])) {
+      set_error("gj_weighted_grad_noalloc: null weights or gradient buffer for table %d", t);
+      return GJ_E_INVALID;
+    }
+  // scratch layout: cw, Uw (entry slots), Mw, Dw (group slots), links, one double
+  const int64_t b_slots = align256(Pl.S * (int64_t)sizeof(double));
+  const int64_t b_link = align256(Pl.link_slots * (int64_t)sizeof(int32_t));
+  const int64_t need = 4 * b_slots + b_link + 256;
+  if (need > (int64_t)GJ_NOALLOC_SCRATCH_BYTES) {
+    set_error("gj_weighted_grad_noalloc: the query needs %lld bytes of scratch, more than the %lld available "
+              "(about %lld rows in all); use gj_weighted_forward / gj_weighted_backward",
+              (long long)need, (long long)GJ_NOALLOC_SCRATCH_BYTES,
+              (long long)(GJ_NOALLOC_SCRATCH_BYTES / 36));
+    return GJ_E_INVALID;
+  }
+  unsigned char* base = nullptr;
+  gj_status st = scratch_address(ctx, &base);
+  if (st) return st;
+  WPtrs P{};
+  for (int t = 0; t < Pl.nt; ++t) P.w[t] = w[t];
+  P.cw = reinterpret_cast<double*>(base);
+  P.Uw = reinterpret_cast<double*>(base + b_slots);
+  P.Mw = reinterpret_cast<double*>(base + 2 * b_slots);
+  P.Dw = reinterpret_cast<double*>(base + 3 * b_slots);
+  P.link = reinterpret_cast<int32_t*>(base + 4 * b_slots);
+  double* one = reinterpret_cast<double*>(base + 4 * b_slots + b_link);
+  P.W = d_W;
+  P.dtype = w_dtype;
+  GPtrs G{};
+  for (int t = 0; t < Pl.nt; ++t) G.g[t] = grad_w[t];
+  hipStream_t s = ctx->stream;
+  // what accumulates starts at zero (fill kernels, no memset: the call may be
+  // recorded into a graph)
+  fill_f64(s, P.Mw, Pl.S, 0.0);
+  fill_f64(s, P.Dw, Pl.S, 0.0);
+  fill_f64(s, P.cw, Pl.S, 0.0);
+  fill_f64(s, d_W, 1, 0.0);
+  if (!d_gradW) {
+    fill_f64(s, one, 1, 1.0);
+    d_gradW = one;
+  }
+  if (Pl.all.n > 0)
+    hipLaunchKernelGGL(k_wcount, dim3(Pl.all.n), dim3(GJ_BLOCK), 0, s, Pl.d_wl + Pl.all.off, Pl.d_desc, f->F, P);
+  for (int h = 0; h <= Pl.max_height; ++h) {
+    const WL& l = Pl.up[h];
+    if (l.n > 0) hipLaunchKernelGGL(k_wup, dim3(l.n), dim3(GJ_BLOCK), 0, s, Pl.d_wl + l.off, Pl.d_desc, f->F, P);
+  }
+  for (int dd = 1; dd <= Pl.max_depth; ++dd) {
+    const WL& l = Pl.down[dd];
+    if (l.n > 0) hipLaunchKernelGGL(k_wdown, dim3(l.n), dim3(GJ_BLOCK), 0, s, Pl.d_wl + l.off, Pl.d_desc, f->F, P);
+  }
+  if (Pl.all.n > 0)
+    hipLaunchKernelGGL(k_wgrad, dim3(Pl.all.n), dim3(GJ_BLOCK), 0, s, Pl.d_wl + Pl.all.off, Pl.d_desc, f->F, P,
+                       d_gradW, G);
+  return check(hipGetLastError(), "weighted kernels");
+}
 
 
 }  // extern "C"

@@ -107,6 +107,7 @@ SIGNATURES = {
     "gj_weighted_forward": (C.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "gj_weighted_backward": (C.c_int, [_vp, _vp, _vp, _vp]),
     "gj_free_wstate": (None, [_vp]),
+    "gj_weighted_grad_noalloc": (C.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     "gj_batch_create": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "gj_batch_launch": (C.c_int, [_vp, _vp]),
     "gj_batch_launch_eager": (C.c_int, [_vp, _vp]),
@@ -468,6 +469,23 @@ class Context:
     def weighted_backward(self, st: "WState", gradW, grads: List["torch.Tensor"]):
         gp = (C.c_void_p * len(grads))(*[g.data_ptr() for g in grads])
         self._check(self.L.gj_weighted_backward(self.h, st.h, C.c_void_p(gradW.data_ptr()), gp))
+
+    def weighted_grad_noalloc(self, f: "Factors", weights, W, grads, gradW=None):
+        """W into the float64 device scalar `W` and dW/dw into `grads` (one
+        tensor per table, the weights' dtype) in one call that allocates
+        nothing (the library's fixed scratch array); gradW: optional float64
+        device scalar scaling the gradients."""
+        import torch
+
+        dt = weights[0].dtype
+        if dt not in (torch.float32, torch.float64) or any(w.dtype != dt for w in weights) or \
+                any(g.dtype != dt for g in grads) or W.dtype != torch.float64:
+            raise ValueError("weights and gradients of one float dtype, W float64")
+        wp = (C.c_void_p * len(weights))(*[w.data_ptr() for w in weights])
+        gp = (C.c_void_p * len(grads))(*[g.data_ptr() for g in grads])
+        self._check(self.L.gj_weighted_grad_noalloc(self.h, f.h, wp, 1 if dt == torch.float64 else 0,
+                                                    C.c_void_p(gradW.data_ptr()) if gradW is not None else None,
+                                                    C.c_void_p(W.data_ptr()), gp))
 
     # -- batch ---------------------------------------------------------------
     def batch_create(self, queries: List[dict], tune: Optional[Tune] = None) -> "Batch":
