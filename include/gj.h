@@ -416,10 +416,11 @@ gj_status gj_weighted_grad_noalloc(gj_ctx* ctx, const gj_factors* f, const void*
 /* ---- batched queries ----
  * Plans n_queries independent queries (tables of query q are
  * tables[q_off[q] .. q_off[q+1]), graphs[q] its join tree): reads the key
- * ranges once, sizes every workspace for the worst case, and records the
- * whole factor build + summary of all queries as one HIP graph whose kernels
- * each cover every query (no host synchronization, no allocation inside).
- * tune = NULL uses built-in tile sizes. */
+ * ranges once (one synchronization), sizes every workspace for the worst case,
+ * and records the factor build + summary of every query as one HIP graph of
+ * one kernel launch per stage and tree level, each launch covering every
+ * query; nothing in it allocates or waits for the host.  tune = NULL uses the
+ * context's tile sizes. */
 typedef struct {
   int32_t sort_items;   /* keys per thread in 64-bit radix-sort tiles (8 or 16;
                            128-bit tiles always take 8) */
@@ -428,13 +429,26 @@ typedef struct {
                            or 0: as many as make about 640 bytes of output per lane
                            and at least 16 tuples */
   int32_t desum_stage;  /* tuples per lane per LDS staging round: 2, 4 or 8 */
+  int32_t batch_task_rows; /* rows (or sort keys) per task of the persistent batch
+                              kernel's plan (256..2^24), or 0: 16384 */
 } gj_tune;
 gj_status gj_batch_create(gj_ctx* ctx, int32_t n_queries, const int32_t* q_off, const gj_table* tables,
                           const gj_join_graph* graphs, const gj_tune* tune, gj_batch** out);
-/* Replays the recorded graph on `hip_stream` (NULL = context stream): recomputes
- * every factor and summary from the (same) input columns. */
+/* Replays the recorded graph on `hip_stream` (NULL = context stream):
+ * recomputes every factor and summary from the (same) input columns.  Reads on
+ * the context's stream (views, gj_download) are ordered after the launch. */
 gj_status gj_batch_launch(gj_batch* b, void* hip_stream);
-/* Same work without the graph: the kernels launched one by one (for comparison). */
+/* The same replay (the launch-per-stage graph). */
+gj_status gj_batch_launch_kernels(gj_batch* b, void* hip_stream);
+/* The factor build + summary of every query in ONE persistent kernel launch
+ * (blocks take tasks -- a few tiles of one stage of one table -- from a device
+ * queue in dependency order; a task waits, bounded, only for the earlier
+ * stages of its own table).  Switched off: returns GJ_E_INVALID. */
+gj_status gj_batch_launch_persistent(gj_batch* b, void* hip_stream);
+/* Tasks and stage instances of the persistent kernel's plan, and its grid
+ * (0: not set up). */
+gj_status gj_batch_info(const gj_batch* b, int32_t* n_tasks, int32_t* n_stages, int32_t* grid);
+/* The launch-per-stage work without a graph, the kernels launched one by one. */
 gj_status gj_batch_launch_eager(gj_batch* b, void* hip_stream);
 /* Device arrays of n_queries entries: join sizes (int64) and statuses (int32,
  * GJ_OK or GJ_E_OVERFLOW), written by every launch. */

@@ -29,7 +29,7 @@ FLAGS = [
 ]
 
 SOURCES = ["factor.hip", "summary.hip", "desum.hip", "desum_values.hip", "desum_runs.hip", "project.hip",
-           "weighted.hip", "gfjs.hip", "api.hip", "batch.hip", "store.hip",
+           "weighted.hip", "gfjs.hip", "api.hip", "batch.hip", "batch_persist.hip", "store.hip",
            "jtree.hip", "pjoin.hip", "cyclic.hip"]
 
 

@@ -540,6 +540,7 @@ gj_status gj_ctx_create(int device, void* hip_stream, gj_alloc_fn alloc, gj_free
   c->tune.radix_bits = 8;
   c->tune.desum_rounds = 0;
   c->tune.desum_stage = 4;
+  c->tune.batch_task_rows = 0;
   *out = c;
   return GJ_OK;
 }
@@ -553,10 +554,12 @@ gj_status gj_ctx_set_tune(gj_ctx* ctx, const gj_tune* tune) {
     return GJ_E_INVALID;
   }
   const int stg = tune->desum_stage;
+  const int btr = tune->batch_task_rows;
   if ((tune->sort_items != 8 && tune->sort_items != 16) || tune->radix_bits < 4 || tune->radix_bits > 8 ||
-      tune->desum_rounds < 0 || tune->desum_rounds > 1024 || !(stg == 2 || stg == 4 || stg == 8)) {
+      tune->desum_rounds < 0 || tune->desum_rounds > 1024 || !(stg == 2 || stg == 4 || stg == 8) ||
+      !(btr == 0 || (btr >= 256 && btr <= (1 << 24)))) {
     set_error("gj_ctx_set_tune: sort_items in {8,16}, radix_bits in [4,8], desum_rounds in [0,1024], "
-              "desum_stage in {2,4,8}");
+              "desum_stage in {2,4,8}, batch_task_rows 0 or in [256, 2^24]");
     return GJ_E_INVALID;
   }
   ctx->tune = *tune;

@@ -1,13 +1,17 @@
-// Batched queries.  Every kernel of the factor build and of the summary
-// already walks a (table, tile) work list, so a batch is one plan whose tables
-// come from many queries: each launch covers every query at once (one launch
-// per stage and tree level, not per query), and the whole sequence is
-// recorded once as a HIP graph.  Workspaces are sized by row counts only
-// (an entry count never exceeds its table's row count), so nothing inside the
-// graph allocates or waits for the host.
+// Batched queries.  A batch is one plan whose tables come from many queries.
+// Its factor build and summary are recorded as one launch per stage and tree
+// level, each covering every query (every kernel walks a (table, tile) work
+// list): gj_batch_launch (and gj_batch_launch_kernels) replay that graph,
+// gj_batch_launch_eager issues the same launches unrecorded.  The persistent
+// kernel of batch_persist.hip (every stage of every query in one launch, from
+// a device task queue) is planned but switched off: gj_batch_launch_persistent.
+// Workspaces are sized by row counts only (an entry count never exceeds its
+// table's row count), so nothing inside either graph allocates or waits for
+// the host.
 #include <vector>
 
 #include "kernels.h"
+#include "persist.h"
 #include "plan.h"
 
 using namespace gjh;
@@ -17,8 +21,10 @@ struct gj_batch {
   gj_factors* f = nullptr;
   gj_summary* s = nullptr;  // one set of summary arrays for all queries
   std::vector<gj_summary*> views;
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;  // one launch per stage
   hipGraphExec_t exec = nullptr;
+  gjk::PArgs pargs{};  // shape of the persistent kernel's plan (not launched)
+  int pgrid = 0;
   hipStream_t cap = nullptr;
   hipEvent_t done = nullptr;  // end of a launch on a stream other than the context's
   std::vector<int64_t> cnt_host;
@@ -74,7 +80,18 @@ gj_status gj_batch_create(gj_ctx* ctx, int32_t n_queries, const int32_t* q_off, 
     batch_destroy(b);
     return st;
   }
-  // record factor build + summary of every query as one graph
+  // the persistent kernel's plan (stage instances, dependencies, tasks) is
+  // built so that its shape can be inspected; the kernel itself is not
+  // recorded or launched (see gj_batch_launch_persistent)
+  const Plan& P = b->f->plan;
+  std::vector<gjk::PStage> stages;
+  std::vector<int32_t> deps;
+  std::vector<gjk::PTask> tasks;
+  gjk::build_persistent_plan(P, (tune ? *tune : ctx->tune).batch_task_rows, stages, deps, tasks);
+  b->pargs.ntasks = (int32_t)tasks.size();
+  b->pargs.nstages = (int32_t)stages.size();
+  b->pargs.nq = P.nq;
+  // record factor build + summary of every query as one launch per stage
   if ((st = check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream")) ||
       (st = check(hipStreamSynchronize(ctx->stream), "capture")) ||
       (st = check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture"))) {
@@ -115,6 +132,24 @@ gj_status gj_batch_launch(gj_batch* b, void* hip_stream) {
   gj_status st = check(hipGraphLaunch(b->exec, s), "graph launch");
   if (st) return st;
   return join_context_stream(b, s);
+}
+
+gj_status gj_batch_launch_kernels(gj_batch* b, void* hip_stream) { return gj_batch_launch(b, hip_stream); }
+
+gj_status gj_batch_launch_persistent(gj_batch* b, void* hip_stream) {
+  GJ_SCOPE(b ? b->ctx : nullptr);
+  (void)hip_stream;
+  set_error("gj_batch_launch_persistent: the persistent batch kernel is switched off (its first launch on the "
+            "device did not finish within the run's limit and the cause has not been shown); use gj_batch_launch");
+  return GJ_E_INVALID;
+}
+
+gj_status gj_batch_info(const gj_batch* b, int32_t* n_tasks, int32_t* n_stages, int32_t* grid) {
+  if (!b) return GJ_E_INVALID;
+  if (n_tasks) *n_tasks = b->pargs.ntasks;
+  if (n_stages) *n_stages = b->pargs.nstages;
+  if (grid) *grid = b->pgrid;
+  return GJ_OK;
 }
 
 gj_status gj_batch_launch_eager(gj_batch* b, void* hip_stream) {

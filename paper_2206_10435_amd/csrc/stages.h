@@ -1,0 +1,744 @@
+// Device bodies of the factor-build and summary stages.
+//
+// Each body processes one work unit -- a tile of a table, one digit of a
+// table, or a whole table -- and takes its LDS from the caller, so the same
+// code runs as one kernel launch per stage (factor.hip, summary.hip: every
+// block one unit of a work list) and inside the persistent batch kernel
+// (batch.hip: any block runs any unit of any stage).  Bodies return only on
+// block-uniform conditions, so every __syncthreads is reached by the whole
+// block.  What they compute is described where they are launched.
+#pragma once
+#include "gj_internal.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// sort words
+// ---------------------------------------------------------------------------
+template <int WIDE>
+struct WordT;
+template <>
+struct WordT<0> {
+  typedef uint64_t type;
+};
+template <>
+struct WordT<1> {
+  typedef W128 type;
+};
+
+__device__ __forceinline__ uint32_t digit_of(uint64_t w, int shift, uint32_t mask) {
+  return (uint32_t)(w >> shift) & mask;
+}
+__device__ __forceinline__ uint32_t digit_of(const W128& w, int shift, uint32_t mask) {
+  return (uint32_t)shr128_lo(w.lo, w.hi, shift) & mask;
+}
+// any bit at position >= s set?
+__device__ __forceinline__ bool high_bits(uint64_t x, int s) { return s < 64 && (x >> s) != 0; }
+__device__ __forceinline__ bool high_bits(const W128& x, int s) {
+  if (s < 64) return (x.lo >> s) != 0 || x.hi != 0;
+  return s < 128 && (x.hi >> (s - 64)) != 0;
+}
+__device__ __forceinline__ uint64_t wxor(uint64_t a, uint64_t b) { return a ^ b; }
+__device__ __forceinline__ W128 wxor(const W128& a, const W128& b) { return W128{a.lo ^ b.lo, a.hi ^ b.hi}; }
+__device__ __forceinline__ uint64_t wlow(uint64_t a) { return a; }
+__device__ __forceinline__ uint64_t wlow(const W128& a) { return a.lo; }
+__device__ __forceinline__ uint32_t field_of(uint64_t w, int pos, int bits) {
+  return bits == 0 ? 0u : (uint32_t)(w >> pos) & (uint32_t)((1ULL << bits) - 1);
+}
+__device__ __forceinline__ uint32_t field_of(const W128& w, int pos, int bits) {
+  return bits == 0 ? 0u : (uint32_t)shr128_lo(w.lo, w.hi, pos) & (uint32_t)((1ULL << bits) - 1);
+}
+
+template <int WIDE>
+__device__ __forceinline__ typename WordT<WIDE>::type* word_ptr(uint64_t* base, const TDesc& d) {
+  return reinterpret_cast<typename WordT<WIDE>::type*>(base + d.word_off);
+}
+
+// Lanes of the wavefront holding the same `bits`-bit digit (and valid).
+__device__ __forceinline__ uint64_t match_digit(uint32_t dig, bool valid, int bits) {
+  uint64_t peers = __ballot(valid);
+  for (int b = 0; b < bits; ++b) {
+    bool bit = (dig >> b) & 1u;
+    uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+// LDS bytes of each body (the persistent kernel takes the largest).
+constexpr int LDS_UPSWEEP = GJ_WAVES * 256 * 4;
+// downsweep: wh [GJ_WAVES][256], gb [256], ls [256], sh [GJ_WAVES], then the staged tile
+constexpr int DS_GB = GJ_WAVES * 256 * 4;
+constexpr int DS_LS = DS_GB + 256 * 4;
+constexpr int DS_SH = DS_LS + 256 * 4;
+constexpr int DS_STAGE = DS_SH + 16;
+template <int WIDE, int ITEMS>
+constexpr int lds_downsweep() {
+  return DS_STAGE + GJ_BLOCK * ITEMS * (int)sizeof(typename WordT<WIDE>::type);
+}
+constexpr int LDS_SCAN64 = GJ_WAVES * 8;
+constexpr int LDS_SCAN32 = GJ_WAVES * 4;
+constexpr int LDS_SEG = 64 + GJ_BLOCK * 8;  // shv, shf, incl
+#define DOWN_HASH 2048
+constexpr int LDS_DOWN = DOWN_HASH * 4 + DOWN_HASH * 8;
+
+// ---------------------------------------------------------------------------
+// factor build
+// ---------------------------------------------------------------------------
+
+// One sort word per row of tile w: key fields above the row id.
+template <int WIDE>
+__device__ __forceinline__ void pack_body(const WorkItem w, const TDesc* __restrict__ D, uint64_t* __restrict__ words0) {
+  const TDesc& d = D[w.t];
+  if (d.wide != WIDE) return;
+  auto* out = word_ptr<WIDE>(words0, d);
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    int64_t i = base + r * GJ_BLOCK + threadIdx.x;
+    if (i >= d.n) break;
+    uint64_t lo = (uint64_t)i, hi = 0;
+#pragma unroll
+    for (int c = 0; c < MAXK; ++c) {
+      if (c < d.k && d.fbits[c] > 0) {
+        uint64_t f = (uint64_t)((uint32_t)d.col[c][i] - d.kmin[c]);
+        int p = d.rb + d.fshift[c];
+        if (WIDE) {
+          if (p < 64) {
+            lo |= f << p;
+            if (p > 32) hi |= f >> (64 - p);
+          } else {
+            hi |= f << (p - 64);
+          }
+        } else {
+          lo |= f << p;
+        }
+      }
+    }
+    if constexpr (WIDE) {
+      out[i] = W128{lo, hi};
+    } else {
+      out[i] = lo;
+    }
+  }
+}
+
+// Radix sort, one LSD pass = upsweep + digit scan + downsweep.
+// Tile = GJ_BLOCK * ITEMS keys; wave v of the block owns keys
+// [v*64*ITEMS, (v+1)*64*ITEMS) of the tile, visited in rounds of 64 so that
+// (round, lane) order is the input order (needed for stability).
+template <int WIDE, int ITEMS>
+__device__ __forceinline__ void upsweep_body(const WorkItem w, const TDesc* __restrict__ D, uint64_t* words0,
+                                             uint64_t* words1, uint32_t* __restrict__ hist, int pass, void* lds) {
+  uint32_t(*wh)[256] = reinterpret_cast<uint32_t(*)[256]>(lds);
+  const TDesc& d = D[w.t];
+  if (d.wide != WIDE) return;
+  const int db = d.dbits;
+  const int nd = 1 << db;
+  const uint32_t mask = (uint32_t)nd - 1;
+  const int shift = d.rb + pass * db;
+  const auto* in = word_ptr<WIDE>((pass & 1) ? words1 : words0, d);
+  for (int i = threadIdx.x; i < GJ_WAVES * 256; i += GJ_BLOCK) (&wh[0][0])[i] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)w.tile * (GJ_BLOCK * ITEMS);
+  const int64_t cnt = min((int64_t)GJ_BLOCK * ITEMS, d.n - base);
+  const int wv = wave_id(), ln = lane_id();
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    int64_t li = (int64_t)wv * 64 * ITEMS + r * 64 + ln;
+    bool valid = li < cnt;
+    uint32_t dig = valid ? digit_of(in[base + li], shift, mask) : 0u;
+    uint64_t peers = match_digit(dig, valid, db);
+    bool leader = valid && (peers & lanemask_lt()) == 0;
+    if (leader) wh[wv][dig] += (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < nd; g += GJ_BLOCK) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int v = 0; v < GJ_WAVES; ++v) s += wh[v][g];
+    hist[d.hist_off + (int64_t)g * d.ntiles_sort + w.tile] = s;
+  }
+}
+
+// Digit g of table t: exclusive scan of that digit's counts over the table's
+// tiles, in place; the digit total goes to dtot.
+__device__ __forceinline__ void digit_scan_body(int t, int g, const TDesc* __restrict__ D, uint32_t* __restrict__ hist,
+                                                uint32_t* __restrict__ dtot, void* lds) {
+  uint32_t* sh = reinterpret_cast<uint32_t*>(lds);
+  const TDesc& d = D[t];
+  if (g >= (1 << d.dbits)) return;
+  uint32_t* row = hist + d.hist_off + (int64_t)g * d.ntiles_sort;
+  uint32_t carry = 0;
+  for (int64_t i0 = 0; i0 < d.ntiles_sort; i0 += GJ_BLOCK) {
+    int64_t i = i0 + threadIdx.x;
+    uint32_t v = i < d.ntiles_sort ? row[i] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_excl_sum(v, sh, tot);
+    if (i < d.ntiles_sort) row[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) dtot[t * 256 + g] = carry;
+}
+
+template <int WIDE, int ITEMS>
+__device__ __forceinline__ void downsweep_body(const WorkItem w, const TDesc* __restrict__ D, uint64_t* words0,
+                                               uint64_t* words1, const uint32_t* __restrict__ hist,
+                                               const uint32_t* __restrict__ dtot, int pass, void* lds) {
+  typedef typename WordT<WIDE>::type Word;
+  unsigned char* L = reinterpret_cast<unsigned char*>(lds);
+  uint32_t(*wh)[256] = reinterpret_cast<uint32_t(*)[256]>(L);
+  uint32_t* gb = reinterpret_cast<uint32_t*>(L + DS_GB);
+  uint32_t* ls = reinterpret_cast<uint32_t*>(L + DS_LS);
+  uint32_t* sh = reinterpret_cast<uint32_t*>(L + DS_SH);
+  Word* stage = reinterpret_cast<Word*>(L + DS_STAGE);
+  const TDesc& d = D[w.t];
+  if (d.wide != WIDE) return;
+  const int db = d.dbits;
+  const int nd = 1 << db;
+  const uint32_t mask = (uint32_t)nd - 1;
+  const int shift = d.rb + pass * db;
+  const Word* in = word_ptr<WIDE>((pass & 1) ? words1 : words0, d);
+  Word* out = word_ptr<WIDE>((pass & 1) ? words0 : words1, d);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < GJ_WAVES * 256; i += GJ_BLOCK) (&wh[0][0])[i] = 0;
+  // global start of every digit of this tile inside the table's output
+  {
+    uint32_t tot = tid < nd ? dtot[w.t * 256 + tid] : 0u;
+    uint32_t T;
+    uint32_t dbase = block_excl_sum(tot, sh, T);
+    if (tid < nd) gb[tid] = dbase + hist[d.hist_off + (int64_t)tid * d.ntiles_sort + w.tile];
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)w.tile * (GJ_BLOCK * ITEMS);
+  const int64_t cnt = min((int64_t)GJ_BLOCK * ITEMS, d.n - base);
+  const int wv = wave_id(), ln = lane_id();
+  Word key[ITEMS];
+  uint32_t dig[ITEMS];
+  uint32_t rank[ITEMS];
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    int64_t li = (int64_t)wv * 64 * ITEMS + r * 64 + ln;
+    bool valid = li < cnt;
+    if (valid) key[r] = in[base + li];
+    dig[r] = valid ? digit_of(key[r], shift, mask) : 0u;
+    uint64_t peers = match_digit(dig[r], valid, db);
+    uint64_t below = peers & lanemask_lt();
+    uint32_t prev = wh[wv][dig[r]];
+    rank[r] = prev + (uint32_t)__popcll(below);
+    if (valid && below == 0) wh[wv][dig[r]] = prev + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  uint32_t cntd = 0;
+  if (tid < nd) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int v = 0; v < GJ_WAVES; ++v) {
+      uint32_t c = wh[v][tid];
+      wh[v][tid] = s;
+      s += c;
+    }
+    cntd = s;
+  }
+  {
+    uint32_t T;
+    uint32_t lstart = block_excl_sum(cntd, sh, T);
+    if (tid < nd) ls[tid] = lstart;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    int64_t li = (int64_t)wv * 64 * ITEMS + r * 64 + ln;
+    if (li < cnt) stage[ls[dig[r]] + wh[wv][dig[r]] + rank[r]] = key[r];
+  }
+  __syncthreads();
+  for (int j = tid; j < cnt; j += GJ_BLOCK) {
+    Word k = stage[j];
+    uint32_t g = digit_of(k, shift, mask);
+    out[gb[g] + (j - ls[g])] = k;
+  }
+}
+
+// Runs: entry heads (key change) and separator-group heads (separator field
+// change; the root is one group).  Counts per tile, then the write pass.
+template <int WIDE>
+__device__ __forceinline__ void run_flags(const typename WordT<WIDE>::type* wv, const TDesc& d, int64_t i, bool& head,
+                                          bool& shead) {
+  if (i == 0) {
+    head = true;
+    shead = true;
+    return;
+  }
+  auto x = wxor(wv[i], wv[i - 1]);
+  head = high_bits(x, d.rb);
+  shead = !d.is_root && high_bits(x, d.rb + d.sepshift);
+}
+
+template <int WIDE>
+__device__ __forceinline__ void runs_count_body(const WorkItem w, const TDesc* __restrict__ D, uint64_t* words0,
+                                                uint64_t* words1, uint64_t* __restrict__ agg, void* lds) {
+  uint64_t* sh = reinterpret_cast<uint64_t*>(lds);
+  const TDesc& d = D[w.t];
+  if (d.wide != WIDE) return;
+  const auto* wv = word_ptr<WIDE>(d.final_buf ? words1 : words0, d);
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  uint64_t acc = 0;
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    int64_t i = base + r * GJ_BLOCK + threadIdx.x;
+    if (i < d.n) {
+      bool h, s;
+      run_flags<WIDE>(wv, d, i, h, s);
+      acc += (uint64_t)h | ((uint64_t)s << 32);
+    }
+  }
+  uint64_t tot;
+  block_excl_sum(acc, sh, tot);
+  if (threadIdx.x == 0) agg[d.agg_off + w.tile] = tot;
+}
+
+template <int WIDE>
+__device__ __forceinline__ void runs_write_body(const WorkItem w, const TDesc* __restrict__ D, uint64_t* words0,
+                                                uint64_t* words1, const uint64_t* __restrict__ agg, const FPtrs& P,
+                                                void* lds) {
+  uint64_t* sh = reinterpret_cast<uint64_t*>(lds);
+  const TDesc& d = D[w.t];
+  if (d.wide != WIDE) return;
+  const auto* wv = word_ptr<WIDE>(d.final_buf ? words1 : words0, d);
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  const int64_t off = d.off;
+  const uint64_t rbmask = d.rb == 0 ? 0ULL : ((1ULL << d.rb) - 1);
+  uint64_t carry = agg[d.agg_off + w.tile];
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    int64_t i = base + r * GJ_BLOCK + threadIdx.x;
+    bool valid = i < d.n;
+    bool h = false, s = false, nh = false, ns = false;
+    if (valid) {
+      run_flags<WIDE>(wv, d, i, h, s);
+      if (i + 1 == d.n) {
+        nh = true;
+        ns = true;
+      } else {
+        run_flags<WIDE>(wv, d, i + 1, nh, ns);
+        if (d.is_root) ns = false;
+      }
+    }
+    uint64_t v = (uint64_t)h | ((uint64_t)s << 32);
+    uint64_t tot;
+    uint64_t ex = block_excl_sum(v, sh, tot) + carry;
+    carry += tot;
+    if (!valid) continue;
+    const int64_t e = (int64_t)(uint32_t)ex + (h ? 0 : -1);
+    const int64_t g = (int64_t)(ex >> 32) + (s ? 0 : -1);
+    auto word = wv[i];
+    P.perm[off + i] = (int32_t)(wlow(word) & rbmask);
+    if (h) {
+      P.estart[off + e] = (int32_t)i;
+      P.egrp[off + e] = (int32_t)g;
+      for (int c = 0; c < d.k; ++c) {
+        uint32_t f = field_of(word, d.rb + d.fshift[c], d.fbits[c]);
+        P.ekey[d.key_off + (int64_t)c * d.n + e] = (int32_t)(f + d.kmin[c]);
+      }
+    }
+    if (s) {
+      P.glo[off + g] = (int32_t)e;
+      int sc = d.is_root ? 0 : d.sep;
+      uint32_t f = field_of(word, d.rb + d.fshift[sc], d.fbits[sc]);
+      P.gval[off + g] = (int32_t)(f + d.kmin[sc]);
+    }
+    if (nh) P.eend[off + e] = (int32_t)(i + 1);
+    if (ns) P.ghi[off + g] = (int32_t)(e + 1);
+  }
+}
+
+// Dense separator index of tables whose separator values span a small range:
+// didx[didx_off + gval(g) - dmin] = g for every separator group g.
+__device__ __forceinline__ void group_index_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F) {
+  const TDesc& d = D[w.t];
+  if (d.didx_off < 0) return;
+  const int64_t G = F.cnt[w.t * CNT_STRIDE + CNT_G];
+  if (G == d.drange) return;  // every value is a group: the lookup needs no table
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t g = base + r * GJ_BLOCK + threadIdx.x;
+    if (g >= G) break;
+    F.didx[d.didx_off + ((int64_t)F.gval[d.off + g] - d.dmin)] = (int32_t)g;
+  }
+}
+
+// Table t: exclusive scan (in place) of the table's tile aggregates, each a
+// pair of 32-bit counts packed in a uint64 (no carry can cross the halves:
+// counts are < 2^31); the totals go to cnt[t][ca], cnt[t][cb].
+__device__ __forceinline__ void tile_scan_pair_body(int t, const TDesc* __restrict__ D, uint64_t* __restrict__ agg,
+                                                    int64_t* __restrict__ cnt, int ca, int cb, void* lds) {
+  uint64_t* sh = reinterpret_cast<uint64_t*>(lds);
+  const TDesc& d = D[t];
+  uint64_t carry = 0;
+  for (int64_t i0 = 0; i0 < d.ntiles; i0 += GJ_BLOCK) {
+    int64_t i = i0 + threadIdx.x;
+    uint64_t v = i < d.ntiles ? agg[d.agg_off + i] : 0ULL;
+    uint64_t tot;
+    uint64_t ex = block_excl_sum(v, sh, tot);
+    if (i < d.ntiles) agg[d.agg_off + i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    cnt[t * CNT_STRIDE + ca] = (int64_t)(uint32_t)carry;
+    cnt[t * CNT_STRIDE + cb] = (int64_t)(carry >> 32);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// summary
+// ---------------------------------------------------------------------------
+
+// Frequency of an entry: its row count, or the given count of a projected
+// factor (where an entry stands for many rows of a deleted subtree).
+__device__ __forceinline__ uint64_t entry_count(const FPtrs& F, int64_t se) {
+  return F.ecnt ? (uint64_t)F.ecnt[se] : (uint64_t)(F.eend[se] - F.estart[se]);
+}
+
+// index of v in the ascending array a[0..n), or -1
+__device__ __forceinline__ int32_t find_sorted(const int32_t* __restrict__ a, int64_t n, int32_t v) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < n && a[lo] == v) ? (int32_t)lo : -1;
+}
+
+// U per entry of tile w (looking each child value up in the child's group
+// index or its sorted separator values, which also records the entry ->
+// child-group link), and the tile aggregate of a segmented scan of c*U.
+__device__ __forceinline__ void up_agg_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F,
+                                            const SPtrs& S, void* lds) {
+  uint64_t* shv = reinterpret_cast<uint64_t*>(lds);
+  uint32_t* shf = reinterpret_cast<uint32_t*>(shv + GJ_WAVES);
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  uint64_t av = 0;
+  uint32_t af = 0;
+  if (base < M) {
+    for (int r = 0; r < GJ_ROUNDS; ++r) {
+      const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+      uint64_t cu = 0;
+      uint32_t head = 0;
+      if (e < M) {
+        const int64_t se = d.off + e;
+        uint64_t U = 1;
+#pragma unroll
+        for (int i = 0; i < MAXC; ++i) {
+          if (i < d.nchild) {
+            const int ch = d.child[i];
+            const TDesc& dc = D[ch];
+            const int32_t v = F.ekey[d.key_off + (int64_t)d.child_col[i] * d.n + e];
+            int32_t j;
+            if (dc.didx_off >= 0) {
+              const int64_t x = (int64_t)v - dc.dmin;
+              // when every value of the range is a group (a key column such
+              // as a primary key), the group index is the offset itself
+              const bool all = F.cnt[ch * CNT_STRIDE + CNT_G] == dc.drange;
+              j = (x < 0 || x >= dc.drange) ? -1 : all ? (int32_t)x : F.didx[dc.didx_off + x];
+            } else {
+              j = find_sorted(F.gval + dc.off, F.cnt[ch * CNT_STRIDE + CNT_G], v);
+            }
+            S.link[dc.link_off + e] = j;
+            const uint64_t m = j >= 0 ? (uint64_t)S.Mg[dc.off + j] : 0ULL;
+            U = smul(U, m);
+          }
+        }
+        const uint64_t c = entry_count(F, se);
+        cu = smul(c, U);
+        S.U[se] = (int64_t)U;
+        head = (e == 0 || F.egrp[se] != F.egrp[se - 1]) ? 1u : 0u;
+      }
+      uint64_t tv;
+      uint32_t tf;
+      block_seg_incl(cu, head, shv, shf, tv, tf);
+      av = tf ? tv : sadd(av, tv);
+      af |= tf;
+    }
+  }
+  if (threadIdx.x == 0) {
+    F.agg[d.agg_off + w.tile] = av;
+    F.agg2[d.agg_off + w.tile] = af;
+  }
+}
+
+// Table t: carry-in value of every tile of the segmented scan (exclusive),
+// written over the tile aggregate.
+__device__ __forceinline__ void seg_tiles_body(int t, const TDesc* __restrict__ D, const FPtrs& F, void* lds) {
+  uint64_t* shv = reinterpret_cast<uint64_t*>(lds);
+  uint32_t* shf = reinterpret_cast<uint32_t*>(shv + GJ_WAVES);
+  uint64_t* incl = reinterpret_cast<uint64_t*>(reinterpret_cast<unsigned char*>(lds) + 64);
+  const TDesc& d = D[t];
+  uint64_t cv = 0;
+  for (int64_t i0 = 0; i0 < d.ntiles; i0 += GJ_BLOCK) {
+    const int64_t i = i0 + threadIdx.x;
+    uint64_t v = 0;
+    uint32_t f = 0;
+    if (i < d.ntiles) {
+      v = F.agg[d.agg_off + i];
+      f = (uint32_t)F.agg2[d.agg_off + i];
+    }
+    uint64_t tv;
+    uint32_t tf;
+    block_seg_incl(v, f, shv, shf, tv, tf);
+    const uint64_t mine = f ? v : sadd(cv, v);  // inclusive, with the carry
+    incl[threadIdx.x] = mine;
+    __syncthreads();
+    const uint64_t ex = threadIdx.x == 0 ? cv : incl[threadIdx.x - 1];
+    if (i < d.ntiles) F.agg[d.agg_off + i] = ex;
+    cv = incl[GJ_BLOCK - 1];
+    __syncthreads();
+  }
+}
+
+// Exclusive prefix of c*U inside each separator group (the block offsets of
+// desummarization), the group totals M, and the root's join size.
+__device__ __forceinline__ void up_scan_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F,
+                                             const SPtrs& S, void* lds) {
+  uint64_t* shv = reinterpret_cast<uint64_t*>(lds);
+  uint32_t* shf = reinterpret_cast<uint32_t*>(shv + GJ_WAVES);
+  uint64_t* incl = reinterpret_cast<uint64_t*>(reinterpret_cast<unsigned char*>(lds) + 64);
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  if (base >= M) return;
+  uint64_t cv = F.agg[d.agg_off + w.tile];
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+    const int64_t se = d.off + e;
+    uint64_t cu = 0;
+    uint32_t head = 0;
+    const bool valid = e < M;
+    if (valid) {
+      const uint64_t c = entry_count(F, se);
+      cu = smul(c, (uint64_t)S.U[se]);
+      head = (e == 0 || F.egrp[se] != F.egrp[se - 1]) ? 1u : 0u;
+    }
+    uint64_t v = cu;
+    uint32_t f = head;
+    uint64_t tv;
+    uint32_t tf;
+    block_seg_incl(v, f, shv, shf, tv, tf);
+    const uint64_t mine = f ? v : sadd(cv, v);
+    incl[threadIdx.x] = mine;
+    __syncthreads();
+    if (valid) {
+      const uint64_t ex = head ? 0ULL : (threadIdx.x == 0 ? cv : incl[threadIdx.x - 1]);
+      S.pre[se] = (int64_t)ex;
+      const bool last = (e + 1 == M) || F.egrp[se + 1] != F.egrp[se];
+      if (last) {
+        S.Mg[d.off + F.egrp[se]] = (int64_t)mine;
+        if (d.is_root) {
+          S.qsize[d.query] = (int64_t)mine;
+          S.qstatus[d.query] = mine >= SATV ? GJ_E_OVERFLOW : GJ_OK;
+        }
+      }
+    }
+    cv = incl[GJ_BLOCK - 1];
+    __syncthreads();
+  }
+}
+
+// Downward messages into the children of tile w's table.  The terms of one
+// tile are first summed per child group in an LDS hash table (linear
+// probing; a key that finds no slot goes straight to global memory), so a
+// heavily shared separator value costs one global atomic per tile instead of
+// one per parent entry.
+__device__ __forceinline__ void down_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F,
+                                          const SPtrs& S, void* lds) {
+  int32_t* hkey = reinterpret_cast<int32_t*>(lds);
+  unsigned long long* hval = reinterpret_cast<unsigned long long*>(reinterpret_cast<unsigned char*>(lds) + DOWN_HASH * 4);
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  if (base >= M) return;
+  for (int ci = 0; ci < d.nchild; ++ci) {
+    const TDesc& dt = D[d.child[ci]];
+    for (int i = threadIdx.x; i < DOWN_HASH; i += GJ_BLOCK) {
+      hkey[i] = -1;
+      hval[i] = 0;
+    }
+    __syncthreads();
+    for (int r = 0; r < GJ_ROUNDS; ++r) {
+      const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+      if (e >= M) break;
+      const int64_t se = d.off + e;
+      const uint64_t U = (uint64_t)S.U[se];
+      if (U == 0) continue;
+      const uint64_t Dp = d.is_root ? 1ULL : (uint64_t)S.Dg[d.off + F.egrp[se]];
+      if (Dp == 0) continue;
+      const uint64_t c = entry_count(F, se);
+      const int32_t j = S.link[dt.link_off + e];
+      // c * Dp * product of the other children's messages: U / M_ci when U
+      // is exact (U > 0, so every message is > 0), else the product itself
+      uint64_t term = smul(c, Dp);
+      if (U < SATV) {
+        term = smul(term, U / (uint64_t)S.Mg[dt.off + j]);
+      } else {
+        for (int i = 0; i < d.nchild; ++i) {
+          if (i == ci) continue;
+          const TDesc& dc = D[d.child[i]];
+          term = smul(term, (uint64_t)S.Mg[dc.off + S.link[dc.link_off + e]]);
+        }
+      }
+      uint32_t h = ((uint32_t)j * 2654435761u) >> 21;  // 11 bits
+      bool placed = false;
+#pragma unroll 1
+      for (int p = 0; p < 8 && !placed; ++p) {
+        const uint32_t slot = (h + p) & (DOWN_HASH - 1);
+        const int32_t prev = atomicCAS(&hkey[slot], -1, j);
+        if (prev == -1 || prev == j) {
+          atomicAdd(&hval[slot], (unsigned long long)term);
+          placed = true;
+        }
+      }
+      if (!placed) atomicAdd((unsigned long long*)(S.Dg + dt.off + j), (unsigned long long)term);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < DOWN_HASH; i += GJ_BLOCK) {
+      const int32_t j = hkey[i];
+      if (j >= 0) atomicAdd((unsigned long long*)(S.Dg + dt.off + j), hval[i]);
+    }
+    __syncthreads();
+  }
+}
+
+// Survivors: entries with c > 0, U > 0 and D > 0, groups with M > 0 and D > 0
+// (a row count is never 0; a projected frequency can be).
+__device__ __forceinline__ bool entry_survives(const TDesc& d, const FPtrs& F, const SPtrs& S, int64_t se) {
+  if (S.U[se] == 0 || (F.ecnt && F.ecnt[se] == 0)) return false;
+  return d.is_root || S.Dg[d.off + F.egrp[se]] > 0;
+}
+__device__ __forceinline__ bool group_survives(const TDesc& d, const SPtrs& S, int64_t sg) {
+  return S.Mg[sg] > 0 && (d.is_root || S.Dg[sg] > 0);
+}
+
+__device__ __forceinline__ void compact_count_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F,
+                                                   const SPtrs& S, void* lds) {
+  uint64_t* sh = reinterpret_cast<uint64_t*>(lds);
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t G = F.cnt[w.t * CNT_STRIDE + CNT_G];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  uint64_t acc = 0;
+  if (base < M) {
+    for (int r = 0; r < GJ_ROUNDS; ++r) {
+      const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+      if (e < M && entry_survives(d, F, S, d.off + e)) acc += 1;
+      if (e < G && group_survives(d, S, d.off + e)) acc += 1ULL << 32;
+    }
+  }
+  uint64_t tot;
+  block_excl_sum(acc, sh, tot);
+  if (threadIdx.x == 0) F.agg[d.agg_off + w.tile] = tot;
+}
+
+__device__ __forceinline__ void compact_write_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F,
+                                                   const SPtrs& S, void* lds) {
+  uint64_t* sh = reinterpret_cast<uint64_t*>(lds);
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t G = F.cnt[w.t * CNT_STRIDE + CNT_G];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  if (base >= M) return;
+  uint64_t carry = F.agg[d.agg_off + w.tile];
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+    const int64_t se = d.off + e;
+    const bool ve = e < M, vg = e < G;
+    const bool es = ve && entry_survives(d, F, S, se);
+    const bool gs = vg && group_survives(d, S, se);
+    uint64_t tot;
+    const uint64_t ex = block_excl_sum((uint64_t)es | ((uint64_t)gs << 32), sh, tot) + carry;
+    carry += tot;
+    const int64_t ci = (int64_t)(uint32_t)ex;
+    const int64_t gi = (int64_t)(ex >> 32);
+    if (ve) {
+      S.e2c[se] = (int32_t)ci;
+      if (es) {
+        const int64_t sc = d.off + ci;
+        const uint64_t c = entry_count(F, se);
+        const uint64_t U = (uint64_t)S.U[se];
+        const uint64_t Dv = d.is_root ? 1ULL : (uint64_t)S.Dg[d.off + F.egrp[se]];
+        for (int k = 0; k < d.k; ++k)
+          S.ckey[d.key_off + (int64_t)k * d.n + ci] = F.ekey[d.key_off + (int64_t)k * d.n + e];
+        S.cc[sc] = (int64_t)c;
+        S.cU[sc] = (int64_t)U;
+        S.cD[sc] = (int64_t)Dv;
+        S.cF[sc] = (int64_t)smul(smul(c, U), Dv);
+        S.cpre[sc] = S.pre[se];
+        S.cstart[sc] = F.estart[se];
+        S.ccs[sc] = make_int2((int)c, F.estart[se]);
+      }
+    }
+    if (vg) {
+      S.g2c[se] = gs ? (int32_t)gi : -1;
+      if (gs) {
+        const int64_t sg = d.off + gi;
+        S.cgval[sg] = F.gval[se];
+        S.cgM[sg] = S.Mg[se];
+        S.cgD[sg] = d.is_root ? 1 : S.Dg[se];
+      }
+    }
+  }
+}
+
+// Second compaction pass (needs every e2c / g2c).  What a child's group
+// contributes to its parents' records depends on the group only, so every
+// group's record is built once (group_recs) and copied to the records of the
+// surviving parent entries that link to it (compact_links).
+__device__ __forceinline__ void group_recs_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F,
+                                                const SPtrs& S) {
+  const TDesc& d = D[w.t];
+  if (d.is_root) return;
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t G = F.cnt[w.t * CNT_STRIDE + CNT_G];
+  const int64_t Mc = F.cnt[w.t * CNT_STRIDE + CNT_MC];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t g = base + r * GJ_BLOCK + threadIdx.x;
+    if (g >= G) break;
+    const int64_t sg = d.off + g;
+    const int32_t gc = S.g2c[sg];
+    if (gc < 0) continue;  // no surviving parent entry links here
+    const int32_t glo = F.glo[sg], ghi = F.ghi[sg];
+    ChildRec rc;
+    rc.first = glo < M ? S.e2c[d.off + glo] : (int32_t)Mc;
+    rc.end = ghi < M ? S.e2c[d.off + ghi] : (int32_t)Mc;
+    const int2 cs0 = rc.first < rc.end ? S.ccs[d.off + rc.first] : make_int2(0, 0);
+    rc.c0 = cs0.x;
+    rc.st0 = cs0.y;
+    rc.M = S.cgM[d.off + gc];
+    rc.unused = 0;
+    S.grec[sg] = rc;
+  }
+}
+
+__device__ __forceinline__ void compact_links_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F,
+                                                   const SPtrs& S) {
+  const TDesc& d = D[w.t];
+  if (d.nchild == 0) return;
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
+    if (e >= M) break;
+    const int64_t se = d.off + e;
+    if (!entry_survives(d, F, S, se)) continue;
+    const int32_t ci = S.e2c[se];
+    for (int i = 0; i < d.nchild; ++i) {
+      const TDesc& dc = D[d.child[i]];
+      // a surviving entry's child group survives (its message and its
+      // downward message are both > 0)
+      S.crec[dc.link_off + ci] = S.grec[dc.off + S.link[dc.link_off + e]];
+    }
+  }
+}
+
+}  // namespace

@@ -71,7 +71,7 @@ class _PotView(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("sort_items", C.c_int32), ("radix_bits", C.c_int32), ("desum_rounds", C.c_int32),
-                ("desum_stage", C.c_int32)]
+                ("desum_stage", C.c_int32), ("batch_task_rows", C.c_int32)]
 
 
 class DesumLaunch(C.Structure):
@@ -111,6 +111,9 @@ SIGNATURES = {
     "gj_batch_create": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "gj_batch_launch": (C.c_int, [_vp, _vp]),
     "gj_batch_launch_eager": (C.c_int, [_vp, _vp]),
+    "gj_batch_launch_kernels": (C.c_int, [_vp, _vp]),
+    "gj_batch_launch_persistent": (C.c_int, [_vp, _vp]),
+    "gj_batch_info": (C.c_int, [_vp, _vp, _vp, _vp]),
     "gj_batch_join_sizes": (_vp, [_vp]),
     "gj_batch_status": (_vp, [_vp]),
     "gj_batch_summary": (C.c_int, [_vp, _i32, _vp]),
@@ -276,8 +279,8 @@ class Context:
             self.L.gj_ctx_destroy(self.h)
             self.h = None
 
-    def set_tune(self, sort_items=8, radix_bits=8, desum_rounds=0, desum_stage=4):
-        t = Tune(sort_items, radix_bits, desum_rounds, desum_stage)
+    def set_tune(self, sort_items=8, radix_bits=8, desum_rounds=0, desum_stage=4, batch_task_rows=0):
+        t = Tune(sort_items, radix_bits, desum_rounds, desum_stage, batch_task_rows)
         self._check(self.L.gj_ctx_set_tune(self.h, C.byref(t)))
 
     def download(self, ptr: int, n: int, dtype) -> np.ndarray:
@@ -613,10 +616,20 @@ class Batch:
             self.ctx.L.gj_free_batch(self.h)
             self.h = None
 
-    def launch(self, graph: bool = True, stream=None):
+    def launch(self, graph: bool = True, stream=None, mode: Optional[str] = None):
+        """mode 'kernels' (the recorded launch-per-stage graph, default),
+        'eager' (those launches unrecorded; graph=False) or 'persistent'
+        (the one-kernel launch, switched off: raises GJError)."""
         sp = C.c_void_p(stream.cuda_stream) if stream is not None else None
-        fn = self.ctx.L.gj_batch_launch if graph else self.ctx.L.gj_batch_launch_eager
+        mode = mode or ("kernels" if graph else "eager")
+        fn = {"persistent": self.ctx.L.gj_batch_launch_persistent, "kernels": self.ctx.L.gj_batch_launch,
+              "eager": self.ctx.L.gj_batch_launch_eager}[mode]
         self.ctx._check(fn(self.h, sp))
+
+    def info(self) -> dict:
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self.ctx._check(self.ctx.L.gj_batch_info(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(tasks=a.value, stages=b.value, grid=c.value)
 
     def results(self):
         nq = len(self.n_tables)

@@ -1,6 +1,7 @@
-"""Many queries in one plan recorded as a HIP graph: every query's join size,
-status and summary against the oracle; replays of the graph agree with each
-other and with the same kernels launched one by one."""
+"""Many queries in one plan recorded as a HIP graph of one launch per stage:
+every query's join size, status and summary against the oracle; replays of
+the graph agree with each other and with the same kernels launched one by
+one.  The persistent one-kernel form is switched off and refuses to launch."""
 import numpy as np
 import pytest
 
@@ -79,8 +80,8 @@ def test_batch_matches_oracle_and_replays(gctx, oracle_mod):
         assert np.array_equal(got, oracles[i].canonical_result()), i
     # replays: graph, eager, graph again -- identical results every time
     first = (js.copy(), st.copy())
-    for mode in (True, False, True, True):
-        b.launch(graph=mode)
+    for mode in ("kernels", "eager", "kernels", "kernels"):
+        b.launch(mode=mode)
         torch.cuda.synchronize()
         js2, st2 = b.results()
         assert np.array_equal(js2, first[0]) and np.array_equal(st2, first[1]), mode
@@ -121,3 +122,58 @@ def test_batch_with_tune(gctx, oracle_mod):
     js, st = b.results()
     for i, (Q, ovf) in enumerate(ref):
         assert (st[i] == gj.GJ_E_OVERFLOW) if ovf else (st[i] == gj.GJ_OK and js[i] == Q)
+
+
+@pytest.mark.skip(reason="the persistent batch kernel is switched off: its first launch on the device did not "
+                         "finish within the run's silence limit and the cause has not been shown")
+def test_persistent_kernel_every_mode_and_task_size(gctx, oracle_mod):
+    """The persistent kernel at task sizes from one tile to whole tables, with
+    8- and 16-key sort tiles, against the oracle on every replay (with eager
+    work in between), and bit-identical to the launch-per-stage graph."""
+    import torch
+
+    from paper_2206_10435_amd import gj
+
+    qs = _queries(31, 36) + [W.cfg5_query(i) for i in (3, 9)]
+    qs.insert(7, W.chain_query(11, 0, 6, 100_000, 10, 0.0, name="overflow_chain6"))
+    oracles = [oracle_mod.Oracle(q) for q in qs]
+    ref = [o.join_size() for o in oracles]
+    check = [i for i, (Q, ovf) in enumerate(ref) if not ovf][:: 5] + [len(qs) - 2, len(qs) - 1]
+    for si, rows in [(8, 0), (8, 256), (16, 2048), (8, 1 << 20)]:
+        b = gctx.batch_create(_qdicts(qs), tune=gj.Tune(si, 8, 0, 4, rows))
+        info = b.info()
+        _say("case persistent", si, rows, info)
+        assert info["tasks"] > 0 and info["grid"] >= 1
+        kept = None
+        for rep, mode in enumerate(("persistent", "kernels", "persistent", "eager", "persistent")):
+            junk = torch.randn(1 << 18, device="cuda:0").sum()  # eager work between launches
+            b.launch(mode=mode)
+            js, st = b.results()
+            for i, (Q, ovf) in enumerate(ref):
+                if ovf:
+                    assert st[i] == gj.GJ_E_OVERFLOW, (mode, i)
+                else:
+                    assert st[i] == gj.GJ_OK and js[i] == Q, (mode, i, js[i], Q)
+            sums = {i: [b.summary(i).table(t) for t in range(qs[i].n_tables)] for i in check}
+            if kept is None:
+                kept = sums
+                for i in check:
+                    _check_summary(b.summary(i), oracles[i], qs[i])
+            else:
+                for i in check:
+                    for t, (x, y) in enumerate(zip(sums[i], kept[i])):
+                        for k in x:
+                            assert np.array_equal(x[k], y[k]), (mode, rep, i, t, k)
+            del junk
+
+
+def test_persistent_launch_refused_while_switched_off(gctx):
+    from paper_2206_10435_amd import gj
+
+    qs = _queries(37, 4)
+    b = gctx.batch_create(_qdicts(qs))
+    info = b.info()
+    assert info["tasks"] > 0 and info["stages"] > 0
+    with pytest.raises(gj.GJError) as ei:
+        b.launch(mode="persistent")
+    assert ei.value.status == gj.GJ_E_INVALID and "switched off" in str(ei.value)
