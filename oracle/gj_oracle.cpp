@@ -405,6 +405,24 @@ int64_t orc_materialize(void* h, int64_t limit, int32_t* out) {
   return em.count;
 }
 
+// The same DFS with the root's rows restricted to [lo, hi): the result
+// tuples whose root row lies in that range, first `limit` of them in DFS
+// order. Disjoint ranges give disjoint parts of the result (so threads can
+// expand them side by side); [0, N_0) is orc_materialize.
+int64_t orc_materialize_range(void* h, int64_t lo, int64_t hi, int64_t limit, int32_t* out) {
+  State& s = *(State*)h;
+  Emitter em{out, limit, 0, s.n};
+  if (limit <= 0 || s.n == 0) return 0;
+  std::vector<int32_t> rows(s.n);
+  lo = std::max<int64_t>(lo, 0);
+  hi = std::min<int64_t>(hi, s.N[0]);
+  for (int64_t r = lo; r < hi; ++r) {
+    rows[0] = (int32_t)r;
+    if (!dfs(s, 1, rows, em)) break;
+  }
+  return em.count;
+}
+
 // Join result by an all-combinations nested loop (tiny inputs only): every
 // combination of one row per table, kept when it agrees on every edge.
 int64_t orc_brute_force(void* h, int64_t limit, int32_t* out) {
@@ -475,7 +493,9 @@ int64_t orc_check_tuples(void* h, const int64_t* tuples, int64_t count, int thre
     const int64_t lo = count * id / threads, hi = count * (id + 1) / threads;
     for (int64_t i = lo; i < hi; ++i) {
       const int64_t* r = tuples + i * n;
-      if (!valid(r) || (i > 0 && !before(r - n, r))) {
+      // the tuple before a range's first belongs to another range: its row
+      // ids are checked here before they index the tables
+      if (!valid(r) || (i > 0 && ((i == lo && !valid(r - n)) || !before(r - n, r)))) {
         first_bad[id] = i;
         return;
       }
