@@ -306,6 +306,24 @@ gj_status gj_summary_save(gj_ctx* ctx, const gj_summary* s, const char* path, in
                           int64_t* bytes_written);
 gj_status gj_summary_load(gj_ctx* ctx, const char* path, gj_summary** out);
 
+/* Checks a file written by gj_summary_save on the host alone, with no device
+ * and no context: the header and table headers, then every section read in
+ * full with the checks gj_summary_load applies before any copy to the device
+ * (entry counts >= 1; child records, (count, first) pairs and row ids inside
+ * their tables), and no data after the last section.  On success *info (host,
+ * may be NULL) receives the table count, the flags, the join size, each
+ * table's surviving entries and rows, and the file size.  An unreadable,
+ * truncated, inconsistent or longer file: GJ_E_INVALID with the reason in
+ * gj_last_error(NULL). */
+typedef struct {
+  int32_t n_tables, projected, with_rows;
+  int64_t join_size;
+  int64_t entries[GJ_MAX_TABLES];
+  int64_t rows[GJ_MAX_TABLES];
+  int64_t bytes;
+} gj_summary_file_info;
+gj_status gj_summary_file_check(const char* path, gj_summary_file_info* info);
+
 /* ---- cyclic queries: natural joins over named attributes (Sec. 2.2.1, 3.2.1, 3.4) ----
  * A natural-join query names the attribute of every key column: column c of
  * table t carries attribute id attr[t * GJ_MAX_KEYS + c] (>= 0), and all

@@ -72,6 +72,7 @@ gj_status file_to_dev(gj_ctx* ctx, FILE* f, T* dst, size_t bytes, std::vector<ch
     set_error("gj_summary_load: inconsistent summary file (an index out of range)");
     return GJ_E_INVALID;
   }
+  if (!dst) return GJ_OK;  // checking only
   gj_status st = check(hipMemcpyAsync(dst, buf.data(), bytes, hipMemcpyHostToDevice, ctx->stream), "load");
   if (!st) st = check(hipStreamSynchronize(ctx->stream), "load");
   return st;
@@ -100,9 +101,119 @@ bool count_ok(const int64_t* r, size_t n, const int64_t*) {
   return true;
 }
 
+struct FileHdr {
+  int32_t n = 0;
+  bool projected = false, with_rows = false;
+  int64_t join_size = 0;
+  std::vector<TabHdr> th;
+};
+
+// Header and table headers, checked on the host: counts in range, a tree in
+// table order, key columns that exist.
+gj_status read_headers(FILE* f, const char* path, FileHdr& h) {
+  char magic[8];
+  int32_t hdr[4];
+  if (fread(magic, 1, 8, f) != 8 || memcmp(magic, MAGIC, 8) != 0 || fread(hdr, sizeof hdr, 1, f) != 1 ||
+      hdr[0] != VERSION || fread(&h.join_size, 8, 1, f) != 1) {
+    set_error("gj_summary_load: %s is not a summary file of this version", path);
+    return GJ_E_INVALID;
+  }
+  h.n = hdr[1];
+  h.projected = hdr[2] != 0;
+  h.with_rows = hdr[3] != 0;
+  if (h.n < 1 || h.n > GJ_MAX_TABLES || h.join_size < 0) {
+    set_error("gj_summary_load: bad header in %s", path);
+    return GJ_E_INVALID;
+  }
+  h.th.resize(h.n);
+  if (fread(h.th.data(), sizeof(TabHdr), h.n, f) != (size_t)h.n) {
+    set_error("gj_summary_load: truncated file");
+    return GJ_E_INVALID;
+  }
+  for (int t = 0; t < h.n; ++t) {
+    const TabHdr& x = h.th[t];
+    const bool bad = x.k < 1 || x.k > GJ_MAX_KEYS || (t == 0) != (x.parent < 0) || (t > 0 && x.parent >= t) ||
+                     x.entries < 0 || x.groups < 0 || x.rows < 0 || x.rows > INT32_MAX || x.entries > INT32_MAX ||
+                     x.groups > INT32_MAX || (h.with_rows && x.entries > x.rows) ||
+                     (t > 0 && (x.sep < 0 || x.sep >= x.k || x.pcol < 0 || x.pcol >= h.th[x.parent].k));
+    if (bad) {
+      set_error("gj_summary_load: bad table header %d in %s", t, path);
+      return GJ_E_INVALID;
+    }
+  }
+  return GJ_OK;
+}
+
+enum Section { SEC_KEY, SEC_C, SEC_U, SEC_D, SEC_F, SEC_PRE, SEC_GVAL, SEC_GM, SEC_GD, SEC_CREC, SEC_CCS, SEC_ROWS };
+
+// Reads every section in file order, checks the ones whose indices the
+// kernels follow, and copies each to dst(section, table, key column) unless
+// that is null.  The file must end after the last section.
+template <typename DstFn>
+gj_status read_sections(gj_ctx* ctx, FILE* f, const FileHdr& h, DstFn dst) {
+  std::vector<char> buf;
+  gj_status st = GJ_OK;
+  for (int t = 0; t < h.n && !st; ++t) {
+    const TabHdr& x = h.th[t];
+    const int64_t E = x.entries, G = x.groups;
+    for (int c = 0; c < x.k && !st; ++c)
+      st = file_to_dev(ctx, f, static_cast<int32_t*>(dst(SEC_KEY, t, c)), E * 4, buf);
+    if (!st) st = file_to_dev(ctx, f, static_cast<int64_t*>(dst(SEC_C, t, 0)), E * 8, buf, count_ok);
+    const Section cols[4] = {SEC_U, SEC_D, SEC_F, SEC_PRE};
+    for (int i = 0; i < 4 && !st; ++i) st = file_to_dev(ctx, f, static_cast<int64_t*>(dst(cols[i], t, 0)), E * 8, buf);
+    if (t > 0 && !st) {
+      st = file_to_dev(ctx, f, static_cast<int32_t*>(dst(SEC_GVAL, t, 0)), G * 4, buf);
+      if (!st) st = file_to_dev(ctx, f, static_cast<int64_t*>(dst(SEC_GM, t, 0)), G * 8, buf);
+      if (!st) st = file_to_dev(ctx, f, static_cast<int64_t*>(dst(SEC_GD, t, 0)), G * 8, buf);
+      if (!st)
+        st = file_to_dev(ctx, f, static_cast<ChildRec*>(dst(SEC_CREC, t, 0)),
+                         h.th[x.parent].entries * sizeof(ChildRec), buf, crec_ok, &x.entries);
+    }
+    if (h.with_rows && !st) {
+      st = file_to_dev(ctx, f, static_cast<int2*>(dst(SEC_CCS, t, 0)), E * sizeof(int2), buf, ccs_ok, &x.rows);
+      if (!st) st = file_to_dev(ctx, f, static_cast<int32_t*>(dst(SEC_ROWS, t, 0)), x.rows * 4, buf, rows_ok, &x.rows);
+    }
+  }
+  if (!st && fgetc(f) != EOF) {
+    set_error("gj_summary_load: data after the last section");
+    st = GJ_E_INVALID;
+  }
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
+
+gj_status gj_summary_file_check(const char* path, gj_summary_file_info* info) {
+  if (!path) {
+    set_error("gj_summary_file_check: null path");
+    return GJ_E_INVALID;
+  }
+  File fh;
+  fh.f = fopen(path, "rb");
+  if (!fh.f) {
+    set_error("gj_summary_file_check: cannot open %s", path);
+    return GJ_E_INVALID;
+  }
+  FileHdr h;
+  gj_status st = read_headers(fh.f, path, h);
+  if (!st) st = read_sections(nullptr, fh.f, h, [](Section, int, int) -> void* { return nullptr; });
+  if (st) return st;
+  if (info) {
+    *info = gj_summary_file_info{};
+    info->n_tables = h.n;
+    info->projected = h.projected ? 1 : 0;
+    info->with_rows = h.with_rows ? 1 : 0;
+    info->join_size = h.join_size;
+    for (int t = 0; t < h.n; ++t) {
+      info->entries[t] = h.th[t].entries;
+      info->rows[t] = h.th[t].rows;
+    }
+    info->bytes = (int64_t)ftell(fh.f);
+  }
+  return GJ_OK;
+}
 
 gj_status gj_summary_save(gj_ctx* ctx, const gj_summary* s, const char* path, int32_t with_rows,
                           int64_t* bytes_written) {
@@ -186,36 +297,12 @@ gj_status gj_summary_load(gj_ctx* ctx, const char* path, gj_summary** out) {
     set_error("gj_summary_load: cannot open %s", path);
     return GJ_E_INVALID;
   }
-  char magic[8];
-  int32_t hdr[4];
-  int64_t join_size = 0;
-  if (fread(magic, 1, 8, fh.f) != 8 || memcmp(magic, MAGIC, 8) != 0 || fread(hdr, sizeof hdr, 1, fh.f) != 1 ||
-      hdr[0] != VERSION || fread(&join_size, 8, 1, fh.f) != 1) {
-    set_error("gj_summary_load: %s is not a summary file of this version", path);
-    return GJ_E_INVALID;
-  }
-  const int n = hdr[1];
-  const bool projected = hdr[2] != 0, with_rows = hdr[3] != 0;
-  if (n < 1 || n > GJ_MAX_TABLES || join_size < 0) {
-    set_error("gj_summary_load: bad header in %s", path);
-    return GJ_E_INVALID;
-  }
-  std::vector<TabHdr> th(n);
-  if (fread(th.data(), sizeof(TabHdr), n, fh.f) != (size_t)n) {
-    set_error("gj_summary_load: truncated file");
-    return GJ_E_INVALID;
-  }
-  for (int t = 0; t < n; ++t) {
-    const TabHdr& h = th[t];
-    const bool bad = h.k < 1 || h.k > GJ_MAX_KEYS || (t == 0) != (h.parent < 0) || (t > 0 && h.parent >= t) ||
-                     h.entries < 0 || h.groups < 0 || h.rows < 0 || h.rows > INT32_MAX || h.entries > INT32_MAX ||
-                     h.groups > INT32_MAX || (with_rows && h.entries > h.rows) ||
-                     (t > 0 && (h.sep < 0 || h.sep >= h.k || h.pcol < 0 || h.pcol >= th[h.parent].k));
-    if (bad) {
-      set_error("gj_summary_load: bad table header %d in %s", t, path);
-      return GJ_E_INVALID;
-    }
-  }
+  FileHdr H;
+  if (gj_status st = read_headers(fh.f, path, H)) return st;
+  const int n = H.n;
+  const bool projected = H.projected, with_rows = H.with_rows;
+  const int64_t join_size = H.join_size;
+  const std::vector<TabHdr>& th = H.th;
   // a compact layout: table t owns cap_t slots (entries, groups and rows fit)
   gj_factors* f = new gj_factors(ctx);
   f->plan.ctx = ctx;
@@ -285,28 +372,26 @@ gj_status gj_summary_load(gj_ctx* ctx, const char* path, gj_summary** out) {
     gj_free_summary(s);
     return GJ_E_OOM;
   }
-  std::vector<char> buf;
-  gj_status st = GJ_OK;
-  for (int t = 0; t < n && !st; ++t) {
+  int32_t* perm = f->F.perm;
+  auto dst = [&](Section sec, int t, int c) -> void* {
     const TDesc& d = P.td[t];
-    const int64_t E = th[t].entries, G = th[t].groups;
-    for (int c = 0; c < d.k && !st; ++c) st = file_to_dev(ctx, fh.f, S.ckey + d.key_off + (int64_t)c * d.n, E * 4, buf);
-    st = file_to_dev(ctx, fh.f, S.cc + d.off, E * 8, buf, count_ok);
-    int64_t* cols[4] = {S.cU, S.cD, S.cF, S.cpre};
-    for (int i = 0; i < 4 && !st; ++i) st = file_to_dev(ctx, fh.f, cols[i] + d.off, E * 8, buf);
-    if (t > 0 && !st) {
-      st = file_to_dev(ctx, fh.f, S.cgval + d.off, G * 4, buf);
-      if (!st) st = file_to_dev(ctx, fh.f, S.cgM + d.off, G * 8, buf);
-      if (!st) st = file_to_dev(ctx, fh.f, S.cgD + d.off, G * 8, buf);
-      if (!st)
-        st = file_to_dev(ctx, fh.f, S.crec + d.link_off, th[d.parent].entries * sizeof(ChildRec), buf, crec_ok,
-                         &th[t].entries);
+    switch (sec) {
+      case SEC_KEY: return S.ckey + d.key_off + (int64_t)c * d.n;
+      case SEC_C: return S.cc + d.off;
+      case SEC_U: return S.cU + d.off;
+      case SEC_D: return S.cD + d.off;
+      case SEC_F: return S.cF + d.off;
+      case SEC_PRE: return S.cpre + d.off;
+      case SEC_GVAL: return S.cgval + d.off;
+      case SEC_GM: return S.cgM + d.off;
+      case SEC_GD: return S.cgD + d.off;
+      case SEC_CREC: return S.crec + d.link_off;
+      case SEC_CCS: return S.ccs + d.off;
+      case SEC_ROWS: return perm + d.off;
     }
-    if (with_rows && !st) {
-      st = file_to_dev(ctx, fh.f, S.ccs + d.off, E * sizeof(int2), buf, ccs_ok, &th[t].rows);
-      if (!st) st = file_to_dev(ctx, fh.f, f->F.perm + d.off, th[t].rows * 4, buf, rows_ok, &th[t].rows);
-    }
-  }
+    return nullptr;
+  };
+  gj_status st = read_sections(ctx, fh.f, H, dst);
   if (st) {
     gj_free_summary(s);
     return st;

@@ -74,6 +74,12 @@ class Tune(C.Structure):
                 ("desum_stage", C.c_int32), ("batch_task_rows", C.c_int32)]
 
 
+class SummaryFileInfo(C.Structure):
+    _fields_ = [("n_tables", C.c_int32), ("projected", C.c_int32), ("with_rows", C.c_int32),
+                ("join_size", C.c_int64), ("entries", C.c_int64 * 16), ("rows", C.c_int64 * 16),
+                ("bytes", C.c_int64)]
+
+
 class DesumLaunch(C.Structure):
     _fields_ = [("stage", C.c_int32), ("tuples_per_lane", C.c_int32), ("kernel_tables", C.c_int32),
                 ("change_bits", C.c_int32), ("seg_bytes", C.c_int32), ("blocks", C.c_int64),
@@ -129,6 +135,7 @@ SIGNATURES = {
     "gj_desummarize_projected": (C.c_int, [_vp, _vp, _i64, _i64, _vp, _vp]),
     "gj_summary_save": (C.c_int, [_vp, _vp, C.c_char_p, _i32, _vp]),
     "gj_summary_load": (C.c_int, [_vp, C.c_char_p, _vp]),
+    "gj_summary_file_check": (C.c_int, [C.c_char_p, _vp]),
     "gj_junction_tree_build": (C.c_int, [_vp, _vp]),
     "gj_potential_join": (C.c_int, [_vp, _vp, _vp, _vp]),
     "gj_potential_table": (C.c_int, [_vp, _vp]),
@@ -188,6 +195,18 @@ def desum_launch_config(n_tables: int, rowid_bytes: int, n_cols: int, n_rows: in
     _check(L.gj_desum_launch_config(int(n_tables), int(rowid_bytes), int(n_cols), int(n_rows),
                                     C.byref(tune) if tune is not None else None, C.byref(out)))
     return {k: int(getattr(out, k)) for k, _ in DesumLaunch._fields_}
+
+
+def summary_file_check(path: str) -> dict:
+    """Checks a stored summary file on the host (no device): raises GJError if
+    it is unreadable, truncated or inconsistent, else returns its header."""
+    L = load_library()
+    info = SummaryFileInfo()
+    _check(L.gj_summary_file_check(os.fsencode(path), C.byref(info)))
+    n = info.n_tables
+    return {"n_tables": n, "projected": bool(info.projected), "with_rows": bool(info.with_rows),
+            "join_size": int(info.join_size), "entries": [int(info.entries[t]) for t in range(n)],
+            "rows": [int(info.rows[t]) for t in range(n)], "bytes": int(info.bytes)}
 
 
 def _natural_struct(attrs):
