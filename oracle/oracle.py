@@ -58,6 +58,8 @@ def _declare(L):
     L.orc_summary_edge.restype = i64
     L.orc_fanouts.argtypes = [vp, C.c_int, vp]
     L.orc_materialize.argtypes = [vp, i64, vp]
+    L.orc_materialize_range.argtypes = [vp, i64, i64, i64, vp]
+    L.orc_materialize_range.restype = i64
     L.orc_materialize.restype = i64
     L.orc_brute_force.argtypes = [vp, i64, vp]
     L.orc_brute_force.restype = i64
@@ -192,6 +194,25 @@ class Oracle:
         out = np.zeros((max(limit, 1), self.n), dtype=np.int32)
         m = self.L.orc_materialize(self.h, int(limit), _p(out))
         return out[:m]
+
+    def materialize_range(self, lo, hi, limit):
+        """Result tuples whose root row is in [lo, hi), first `limit` in DFS order."""
+        out = np.zeros((max(limit, 1), self.n), dtype=np.int32)
+        m = self.L.orc_materialize_range(self.h, int(lo), int(hi), int(limit), _p(out))
+        return out[:m]
+
+    def materialize_threads(self, limit, threads):
+        """`threads` DFS expansions side by side, thread i over the i-th of
+        `threads` equal ranges of root rows, each writing up to limit/threads
+        tuples into its own buffer (ctypes drops the GIL during the calls).
+        Returns the parts in range order."""
+        import concurrent.futures as cf
+
+        n0 = self.q.n_rows(0)
+        cuts = [n0 * i // threads for i in range(threads + 1)]
+        each = max(1, limit // threads)
+        with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+            return list(ex.map(lambda i: self.materialize_range(cuts[i], cuts[i + 1], each), range(threads)))
 
     def brute_force(self, limit=10**7):
         out = np.zeros((limit, self.n), dtype=np.int32)

@@ -412,3 +412,25 @@ def test_check_tuples_accepts_sorted_result_and_rejects_corruptions(oracle_mod):
                 assert o.check_tuples(brk, 2) == 2
         checked += 1
     assert checked >= 8
+
+
+@pytest.mark.parametrize("q", _tiny_queries()[:8], ids=lambda q: q.name)
+def test_materialize_ranges_partition_the_brute_force_result(oracle_mod, q):
+    """The range DFS (the threaded CPU baseline) against brute force: the
+    tuples of root rows [lo, hi) are exactly the brute-force tuples whose
+    root row lies there, and cut points in any place split the result."""
+    o = oracle_mod.Oracle(q)
+    bf = o.brute_force()
+    n0 = q.n_rows(0)
+    for cuts in ([0, n0], [0, n0 // 2, n0], [0, 1, n0 // 3, n0 - 1, n0]):
+        cuts = sorted(set(max(0, min(n0, c)) for c in cuts))
+        parts = [o.materialize_range(a, b, 10**6) for a, b in zip(cuts, cuts[1:])]
+        for (a, b), p in zip(zip(cuts, cuts[1:]), parts):
+            assert np.array_equal(p, bf[(bf[:, 0] >= a) & (bf[:, 0] < b)]) if len(bf) else len(p) == 0
+    for T in (1, 3):
+        got = o.materialize_threads(10**6 * T, T)
+        assert np.array_equal(np.concatenate(got) if got else bf[:0], bf)
+    # the limit cuts each range's output in DFS order
+    if len(bf) > 2:
+        p = o.materialize_range(0, n0, 2)
+        assert np.array_equal(p, bf[:2])
