@@ -58,10 +58,13 @@ DesumPlan desum_plan(int n_tables, int rowid_bytes, int n_cols, int64_t n_rows, 
   p.stage = ks;
   const int nc = values ? n_cols : n_tables;
   const int wb = values ? 4 : rowid_bytes;
-  // rounds_per_lane 0: about 640 bytes of output per lane, at least 16 tuples
-  // (measured best for tuples of 12 to 64 bytes, row ids or values)
+  // rounds_per_lane 0: about 768 bytes of row ids per lane (measured best for
+  // 4 tables with long runs, 24-32 tuples of 32 B, and for 6 tables with runs
+  // of about 9 tuples, 12-16 tuples of 48 B), about 640 bytes of values, and at
+  // least 16 tuples
   const int tup_bytes = nc * wb;
-  int L = rounds_per_lane > 0 ? rs * rounds_per_lane : std::max(rs, std::max(16, 640 / tup_bytes) / rs * rs);
+  const int lane_bytes = values ? 640 : 768;
+  int L = rounds_per_lane > 0 ? rs * rounds_per_lane : std::max(rs, std::max(16, lane_bytes / tup_bytes) / rs * rs);
   // a smaller per-lane range when the range would not fill the chip
   while (L > rs && n_rows / L < 256LL * 1024) L /= 2;
   L = std::max(rs, L / rs * rs);

@@ -234,6 +234,8 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
   const int64_t tup_bytes = (int64_t)nc * (int64_t)sizeof(WT);
   const int rounds = (L + KS - 1) / KS;
   int64_t done = 0;
+  // row ids tuple 0 of the next round needs (the first round reads them all)
+  uint32_t next0 = (uint32_t)((1ull << N) - 1);
   for (int rd = 0; rd < rounds; ++rd) {
     const int kcnt = (int)max((int64_t)0, min((int64_t)KS, mycnt - done));
     // ---- control: perm positions of the row ids that change ----
@@ -241,7 +243,8 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
     int32_t pos[KS][N];
     static_assert(KS * N <= 64, "change mask is 64 bits");
     using MT = typename std::conditional<KS * N <= 32, uint32_t, uint64_t>::type;
-    MT chg = 0;
+    MT chg = (MT)next0;
+    uint32_t nx = 0;
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
 #pragma unroll
@@ -255,12 +258,18 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
               carry = false;
             else
               r[t] = 0;
-            if (k + 1 < KS) chg |= (MT)1 << ((k + 1) * N + t);
+            if (k + 1 < KS)
+              chg |= (MT)1 << ((k + 1) * N + t);
+            else
+              nx |= 1u << t;
           }
         }
         if (carry) {
           // every row list wrapped: next entry tuple
-          if (k + 1 < KS) chg |= (MT)(((MT)1 << N) - 1) << ((k + 1) * N);
+          if (k + 1 < KS)
+            chg |= (MT)(((MT)1 << N) - 1) << ((k + 1) * N);
+          else
+            nx = (uint32_t)((1ull << N) - 1);
           if (e[tl] + 1 < gh[tl]) {
             // next entry of the innermost group: rows follow the current ones
             st[tl] += c[tl];
@@ -312,10 +321,10 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
         }
       }
     }
-    // the first tuple of a round gathers every row id: in the usual case the
-    // outer tables' ids are the same for all lanes of a wave, so these loads
-    // hit one line (measured faster than carrying the change bits over)
-    chg |= (MT)(((MT)1 << N) - 1);
+    // tuple 0 of the next round reads what the last advance of this round
+    // changed (re-reading every row id at each round start costs a random
+    // line per table and lane when runs are short)
+    next0 = nx;
     // ---- data: gathers of the columns whose table moved (exec-masked), all
     //      issued before the first use, then the round into the wave's staging ----
     int32_t v[KS][NCOL];
