@@ -221,14 +221,26 @@ static void fill_desc_static(Plan& P) {
     d.agg_off = aoff;
     aoff += std::max(d.ntiles, 1);
   }
-  // link regions: table t >= 1 gets one slot per entry of its parent
+  // link regions: table t >= 1 gets one slot per entry of its parent; its
+  // bucket counts one row of parent tiles per bucket
+  int64_t hoff = 0;
   for (int t = 0; t < P.nt; ++t) {
     TDesc& d = P.td[t];
     if (d.parent >= 0) {
       d.link_off = loff;
-      loff = align_up(loff + std::max<int64_t>(P.ht[d.parent].n, 1), 64);
+      const int64_t np = P.ht[d.parent].n;
+      loff = align_up(loff + std::max<int64_t>(np, 1), 64);
+      const int64_t nc = P.ht[t].n;
+      d.dbucketed = nc <= DOWN_MAX_GROUPS && np >= (int64_t)DOWN_PARENT_RATIO * std::max<int64_t>(nc, 1);
+      const int64_t pt = std::max(P.td[d.parent].ntiles, 1);
+      d.dhist_off = hoff;
+      if (d.dbucketed) hoff += (int64_t)(DOWN_BUCKETS + 1) * pt;
+      // reduce blocks take a bucket over up to 2048 parent tiles (about 8 ranges
+      // of tiles for the largest parents)
+      d.dslice = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(GJ_BLOCK, (pt + 7) / 8));
     }
   }
+  P.dhist_slots = std::max<int64_t>(hoff, 64);
   P.S = std::max<int64_t>(off, 64);
   P.key_slots = std::max<int64_t>(koff, 64);
   P.link_slots = std::max<int64_t>(loff, 64);
@@ -380,6 +392,34 @@ gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
       if (P.ht[t].depth == dd - 1 && !P.ht[t].children.empty()) tp.push_back(t);
     P.down.push_back(P.add_list(tp, GJ_TILE, false));
   }
+  // bucket sums of each level: items (child, x) for every bucket of the
+  // child and every range of dslice parent tiles
+  P.dred.assign(1, WL{});
+  P.dfall.assign(1, 0);
+  P.dbuck.assign(1, 0);
+  for (int dd = 1; dd <= P.max_depth; ++dd) {
+    WL l;
+    l.off = (int)P.wl_host.size();
+    l.toff = (int)P.tabs_host.size();
+    char fall = 0, buck = 0;
+    for (int t = 0; t < P.nt; ++t) {
+      if (P.ht[t].depth != dd) continue;
+      const TDesc& d = P.td[t];
+      const int64_t ns =
+          d.dbucketed ? (int64_t)DOWN_BUCKETS * ((std::max(P.td[d.parent].ntiles, 1) + d.dslice - 1) / d.dslice) : 0;
+      for (int64_t i = 0; i < ns; ++i) P.wl_host.push_back(WorkItem{t, (int32_t)i});
+      P.tabs_host.push_back(t);
+      if (d.dbucketed)
+        buck = 1;
+      else
+        fall = 1;
+    }
+    l.n = (int)P.wl_host.size() - l.off;
+    l.tn = (int)P.tabs_host.size() - l.toff;
+    P.dred.push_back(l);
+    P.dfall.push_back(fall);
+    P.dbuck.push_back(buck);
+  }
   // factor buffers
   F.words[0] = A.get_n<uint64_t>(P.word_units);
   F.words[1] = A.get_n<uint64_t>(P.word_units);
@@ -458,10 +498,15 @@ gj_status alloc_summary(const Plan& P, Arena& A, SPtrs& S) {
   S.ccs = A.get_n<int2>(P.S);
   S.crec = A.get_n<ChildRec>(P.link_slots);
   S.grec = A.get_n<ChildRec>(P.S);
+  S.xprod = A.get_n<int64_t>(P.link_slots);
+  S.dkey = A.get_n<int32_t>(P.link_slots);
+  S.dval = A.get_n<int64_t>(P.link_slots);
+  S.dhist = A.get_n<uint32_t>(P.dhist_slots);
   S.qsize = A.get_n<int64_t>(P.nq);
   S.qstatus = A.get_n<int32_t>(P.nq);
   void* all[] = {S.U,  S.pre,    S.Mg,    S.Dg,  S.link, S.e2c,  S.g2c,  S.ckey,  S.cc,    S.cU,   S.cD,
-                 S.cF, S.cpre,   S.cstart, S.cgval, S.cgM, S.cgD,  S.qsize, S.qstatus, S.ccs, S.crec, S.grec};
+                 S.cF, S.cpre,   S.cstart, S.cgval, S.cgM, S.cgD,  S.qsize, S.qstatus, S.ccs, S.crec, S.grec,
+                 S.xprod, S.dkey, S.dval, S.dhist};
   for (void* p : all)
     if (!p) return GJ_E_OOM;
   return GJ_OK;
@@ -477,7 +522,9 @@ void launch_summary(const Plan& P, const FPtrs& F, const SPtrs& S, hipStream_t s
   gjk::fill_i64(s, S.Dg, P.S, 0);
   for (int dd = 1; dd <= P.max_depth; ++dd) {
     const WL& l = P.down[dd];
-    gjk::down_pass(s, P.d_wl + l.off, l.n, P.d_desc, F, S);
+    const WL& r = P.dred[dd];
+    gjk::down_pass(s, P.d_wl + l.off, l.n, P.d_wl + r.off, r.n, P.dbuck[dd] != 0, P.dfall[dd] != 0, P.d_desc, F,
+                   S);
   }
   gjk::compact(s, P.d_wl + P.all.off, P.all.n, P.d_tabs + P.all.toff, P.all.tn, P.d_desc, F, S);
 }

@@ -64,7 +64,23 @@ struct TDesc {
   int64_t didx_off;
   int64_t drange;
   int32_t dmin;
+  // (t >= 1) downward pass by buckets of this table's groups: start of
+  // bucket b's items inside parent tile x at dhist[dhist_off + b *
+  // ntiles(parent) + x] (row DOWN_BUCKETS: the tile's item count); a reduce
+  // block takes one bucket over dslice parent tiles
+  int64_t dhist_off;
+  int32_t dslice;
+  int32_t dbucketed;  // (t >= 1) this table's downward message is summed by buckets
 };
+
+// Downward pass by buckets (buckets of at most 2^12 groups, at most 256
+// buckets): for a child of at most this many rows whose parent has at least
+// DOWN_PARENT_RATIO times as many (a large table's foreign key into a
+// smaller one: few repeats of a child group inside a parent tile for the
+// LDS table of the atomic scatter to merge).
+#define DOWN_MAX_GROUPS (1 << 20)
+#define DOWN_BUCKETS 256
+#define DOWN_PARENT_RATIO 4
 
 // Rows / entries per tile of the flat kernels (rounds of GJ_BLOCK elements).
 #define GJ_ROUNDS 16
@@ -123,6 +139,10 @@ struct SPtrs {
   int2* ccs;  // surviving entry -> (row count, first position in perm)
   ChildRec* crec;  // surviving parent entry -> the child's group (see ChildRec)
   ChildRec* grec;  // (t >= 1) group of t -> its record (the same for every parent entry)
+  int64_t* xprod;  // (t >= 1) parent entry -> product of its other children's messages (link layout)
+  int32_t* dkey;   // (t >= 1) downward items: child group, placed bucket by bucket (link layout)
+  int64_t* dval;   //          and the item's term
+  uint32_t* dhist; // per-(bucket, parent tile) start of the bucket's items in the tile (see TDesc)
   int64_t* qsize;
   int32_t* qstatus;
 };

@@ -29,7 +29,11 @@ void entry_counts(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, co
 void fill_i64(hipStream_t s, int64_t* p, int64_t n, int64_t v);
 void up_pass(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,
              const FPtrs& F, const SPtrs& S);
-void down_pass(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F, const SPtrs& S);
+// One level of the downward pass: wl/nwl the parents' tiles, rwl/nrwl the
+// (child, bucket and tile range) items of the bucket sums; bucketed / scattered:
+// a child of the level takes the bucket sums / the atomic scatter.
+void down_pass(hipStream_t s, const WorkItem* wl, int nwl, const WorkItem* rwl, int nrwl, bool bucketed,
+               bool scattered, const TDesc* D, const FPtrs& F, const SPtrs& S);
 void compact(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,
              const FPtrs& F, const SPtrs& S);
 // copies one query's join size and status (device) to caller arrays

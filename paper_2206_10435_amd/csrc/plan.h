@@ -84,6 +84,10 @@ struct Plan {
   std::vector<WL> sort[2];   // [wide][pass]
   std::vector<WL> up;        // [height]
   std::vector<WL> down;      // [depth]: parents at depth-1 that have children
+  std::vector<WL> dred;      // [depth]: (child at depth, slice) items of the bucket sums
+  std::vector<char> dfall;   // [depth]: a child at this depth takes the atomic scatter
+  std::vector<char> dbuck;   // [depth]: a child at this depth is summed by buckets
+  int64_t dhist_slots = 0;
   WorkItem* d_wl = nullptr;
   int32_t* d_tabs = nullptr;
   TDesc* d_desc = nullptr;

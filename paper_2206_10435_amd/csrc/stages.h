@@ -429,8 +429,10 @@ __device__ __forceinline__ void up_agg_body(const WorkItem w, const TDesc* __res
       if (e < M) {
         const int64_t se = d.off + e;
         uint64_t U = 1;
+        uint64_t mi[MAXC];
 #pragma unroll
         for (int i = 0; i < MAXC; ++i) {
+          mi[i] = 1;
           if (i < d.nchild) {
             const int ch = d.child[i];
             const TDesc& dc = D[ch];
@@ -447,7 +449,24 @@ __device__ __forceinline__ void up_agg_body(const WorkItem w, const TDesc* __res
             }
             S.link[dc.link_off + e] = j;
             const uint64_t m = j >= 0 ? (uint64_t)S.Mg[dc.off + j] : 0ULL;
+            mi[i] = m;
             U = smul(U, m);
+          }
+        }
+        // each child's product of the other children's messages (the
+        // downward pass multiplies it in instead of gathering them again)
+        {
+          uint64_t pre = 1;
+#pragma unroll
+          for (int i = 0; i < MAXC; ++i) {
+            if (i < d.nchild) {
+              uint64_t x = pre;
+#pragma unroll
+              for (int i2 = i + 1; i2 < MAXC; ++i2)
+                if (i2 < d.nchild) x = smul(x, mi[i2]);
+              S.xprod[D[d.child[i]].link_off + e] = (int64_t)x;
+              pre = smul(pre, mi[i]);
+            }
           }
         }
         const uint64_t c = entry_count(F, se);
@@ -550,6 +569,10 @@ __device__ __forceinline__ void up_scan_body(const WorkItem w, const TDesc* __re
 // probing; a key that finds no slot goes straight to global memory), so a
 // heavily shared separator value costs one global atomic per tile instead of
 // one per parent entry.
+// SKIP_BUCKETED: children marked dbucketed are left to the bucketed pass
+// below (the launch-per-stage path); without it every child is scattered
+// here.
+template <bool SKIP_BUCKETED = false>
 __device__ __forceinline__ void down_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F,
                                           const SPtrs& S, void* lds) {
   int32_t* hkey = reinterpret_cast<int32_t*>(lds);
@@ -560,6 +583,7 @@ __device__ __forceinline__ void down_body(const WorkItem w, const TDesc* __restr
   if (base >= M) return;
   for (int ci = 0; ci < d.nchild; ++ci) {
     const TDesc& dt = D[d.child[ci]];
+    if (SKIP_BUCKETED && dt.dbucketed) continue;
     for (int i = threadIdx.x; i < DOWN_HASH; i += GJ_BLOCK) {
       hkey[i] = -1;
       hval[i] = 0;
@@ -606,6 +630,191 @@ __device__ __forceinline__ void down_body(const WorkItem w, const TDesc* __restr
       if (j >= 0) atomicAdd((unsigned long long*)(S.Dg + dt.off + j), hval[i]);
     }
     __syncthreads();
+  }
+}
+
+// ---- downward pass by buckets of the child's groups ----
+// Child table ch of parent t (ch marked dbucketed): every
+// parent entry e with a group j in ch is one item (j, c_e * D_t(e's group) *
+// product of e's other children's messages), 0 when U_e or that D is 0.  A
+// parent tile orders its items by bucket (j >> sh, 2^sh groups a bucket) in
+// LDS and writes them to the tile's own slots in that order, with the start
+// of every bucket; a reduce block then takes one bucket over a range of
+// tiles, sums the bucket's runs per group in LDS and writes the sums to D of
+// the bucket's groups (or adds them, when other tile ranges share the
+// bucket).  Sums of integers: the order of the items does not change them.
+
+// buckets of 2^sh groups, at most DOWN_BUCKETS of them (sh <= 12 below DOWN_MAX_GROUPS)
+__device__ __forceinline__ int down_shift(int64_t G) {
+  int sh = 0;
+  while (((G - 1) >> sh) >= DOWN_BUCKETS) ++sh;
+  return sh;
+}
+constexpr int DOWN_ACC = (DOWN_MAX_GROUPS / DOWN_BUCKETS);  // groups of one bucket at most
+constexpr int DT_STAGE = 2 * DOWN_BUCKETS * 4 + LDS_SCAN32 + 16;
+constexpr int LDS_DTILE = DT_STAGE + GJ_TILE * 12;
+constexpr int DOWN_RTILES = 8 * GJ_BLOCK;  // tiles of one reduce range at most
+constexpr int LDS_DRED = DOWN_ACC * 8 + (2 * DOWN_RTILES + 1) * 4 + LDS_SCAN32 + 12;
+
+// Parent tile: each bucketed child's items in bucket order at the tile's
+// slots [tile * GJ_TILE, ...) of the child's item arrays; bucket b's run
+// starts at dhist[dhist_off + b * ntiles + tile] inside the tile (row
+// DOWN_BUCKETS: the tile's item count).
+__device__ __forceinline__ void down_tile_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F,
+                                               const SPtrs& S, void* lds) {
+  static_assert(GJ_BLOCK == DOWN_BUCKETS, "one thread per bucket");
+  unsigned char* L = reinterpret_cast<unsigned char*>(lds);
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(L);
+  uint32_t* start = cnt + DOWN_BUCKETS;
+  uint32_t* sh = start + DOWN_BUCKETS;
+  int32_t* skey = reinterpret_cast<int32_t*>(L + DT_STAGE);
+  uint64_t* sval = reinterpret_cast<uint64_t*>(skey + GJ_TILE);
+  const TDesc& d = D[w.t];
+  const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
+  const int64_t base = (int64_t)w.tile * GJ_TILE;
+  const int tid = threadIdx.x;
+  bool any = false;
+  for (int ci = 0; ci < d.nchild; ++ci) any |= D[d.child[ci]].dbucketed != 0;
+  if (!any) return;  // uniform: this parent's children take the atomic scatter
+  // the entry part of every item, once per entry: c * D of its group (0 if U = 0)
+  uint64_t cd[GJ_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < GJ_ROUNDS; ++r) {
+    const int64_t e = base + r * GJ_BLOCK + tid;
+    cd[r] = 0;
+    if (e < M) {
+      const int64_t se = d.off + e;
+      const uint64_t U = (uint64_t)S.U[se];
+      const uint64_t Dp = d.is_root ? 1ULL : (uint64_t)S.Dg[d.off + F.egrp[se]];
+      if (U != 0 && Dp != 0) cd[r] = smul(entry_count(F, se), Dp);
+    }
+  }
+  for (int ci = 0; ci < d.nchild; ++ci) {
+    const int ch = d.child[ci];
+    const TDesc& dc = D[ch];
+    if (!dc.dbucketed) continue;
+    const int32_t* link = S.link + dc.link_off;
+    const int shb = down_shift(F.cnt[ch * CNT_STRIDE + CNT_G]);
+    cnt[tid] = 0;
+    __syncthreads();
+    int32_t rk[GJ_ROUNDS];  // rank inside the bucket (-1: no item)
+#pragma unroll
+    for (int r = 0; r < GJ_ROUNDS; ++r) {
+      const int64_t e = base + r * GJ_BLOCK + tid;
+      rk[r] = -1;
+      if (e < M) {
+        const int32_t j = link[e];
+        if (j >= 0) rk[r] = (int32_t)atomicAdd(&cnt[j >> shb], 1u);
+      }
+    }
+    __syncthreads();
+    uint32_t tot;
+    const uint32_t st = block_excl_sum(cnt[tid], sh, tot);
+    start[tid] = st;
+    S.dhist[dc.dhist_off + (int64_t)tid * d.ntiles + w.tile] = st;
+    if (tid == 0) S.dhist[dc.dhist_off + (int64_t)DOWN_BUCKETS * d.ntiles + w.tile] = tot;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < GJ_ROUNDS; ++r) {
+      if (rk[r] < 0) continue;
+      const int64_t e = base + r * GJ_BLOCK + tid;
+      const int32_t j = link[e];
+      const uint32_t p = start[j >> shb] + (uint32_t)rk[r];
+      skey[p] = j;
+      sval[p] = cd[r] ? smul(cd[r], (uint64_t)S.xprod[dc.link_off + e]) : 0ULL;
+    }
+    __syncthreads();
+    int32_t* okey = S.dkey + dc.link_off + base;
+    int64_t* oval = S.dval + dc.link_off + base;
+    for (uint32_t i = tid; i < tot; i += GJ_BLOCK) {
+      okey[i] = skey[i];
+      oval[i] = (int64_t)sval[i];
+    }
+    __syncthreads();
+  }
+}
+
+// Reduce item (child ch, x): bucket x / ns, tile range x % ns of ns ranges of
+// dslice(ch) parent tiles each.  The range's runs of the bucket are laid end
+// to end (prefix of their lengths in LDS) and the block's threads take
+// consecutive items of that sequence, so a wave reads whole lines.
+__device__ __forceinline__ void down_reduce_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F,
+                                                 const SPtrs& S, void* lds) {
+  const int ch = w.t;
+  if (!D[ch].dbucketed) return;
+  unsigned char* L = reinterpret_cast<unsigned char*>(lds);
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(L);
+  uint32_t* rbeg = reinterpret_cast<uint32_t*>(L + DOWN_ACC * 8);  // run start in the flat sequence
+  uint32_t* rsrc = rbeg + DOWN_RTILES + 1;                          // run start in the tile's slots
+  uint32_t* shs = rsrc + DOWN_RTILES;
+  const TDesc& dc = D[ch];
+  const TDesc& dp = D[dc.parent];
+  const int64_t G = F.cnt[ch * CNT_STRIDE + CNT_G];
+  const int sh = down_shift(G);
+  const int nb = G > 0 ? (int)((G - 1) >> sh) + 1 : 0;
+  const int TS = dc.dslice;  // tiles per range (<= DOWN_RTILES)
+  const int ns = (dp.ntiles + TS - 1) / TS;
+  const int b = w.tile / ns;
+  const int x = w.tile - b * ns;
+  if (b >= nb) return;
+  const int64_t Mp = F.cnt[dc.parent * CNT_STRIDE + CNT_M];
+  const int t0 = x * TS;
+  const int nt = (int)max<int64_t>(0, min<int64_t>((int64_t)TS, (Mp + GJ_TILE - 1) / GJ_TILE - t0));
+  if (nt == 0) return;  // uniform: D of the bucket's groups is already 0
+  const int64_t g0 = (int64_t)b << sh;
+  const int ng = (int)min((int64_t)1 << sh, G - g0);
+  for (int i = threadIdx.x; i < ng; i += GJ_BLOCK) acc[i] = 0;
+  const uint32_t* hb = S.dhist + dc.dhist_off + (int64_t)b * dp.ntiles + t0;
+  uint32_t carry = 0;
+  for (int i0 = 0; i0 < nt; i0 += GJ_BLOCK) {
+    const int i = i0 + threadIdx.x;
+    uint32_t s0 = 0, len = 0;
+    if (i < nt) {
+      s0 = hb[i];
+      len = hb[dp.ntiles + i] - s0;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_sum(len, shs, tot);
+    if (i < nt) {
+      rbeg[i] = carry + ex;
+      rsrc[i] = s0;
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) rbeg[nt] = carry;
+  __syncthreads();
+  const int64_t o = dc.link_off + (int64_t)t0 * GJ_TILE;
+  constexpr int U4 = 4;
+  for (uint32_t k0 = 0; k0 < carry; k0 += GJ_BLOCK * U4) {
+    int32_t key[U4];
+    uint64_t val[U4];
+#pragma unroll
+    for (int u = 0; u < U4; ++u) {
+      const uint32_t k = k0 + u * GJ_BLOCK + threadIdx.x;
+      key[u] = -1;
+      if (k < carry) {
+        // run holding flat item k: the last run starting at or before k
+        int lo = 0, hi = nt;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (rbeg[mid] <= k) lo = mid; else hi = mid;
+        }
+        const int64_t at = o + (int64_t)lo * GJ_TILE + rsrc[lo] + (k - rbeg[lo]);
+        key[u] = S.dkey[at];
+        val[u] = (uint64_t)S.dval[at];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U4; ++u)
+      if (key[u] >= 0) atomicAdd(&acc[key[u] - g0], (unsigned long long)val[u]);
+  }
+  __syncthreads();
+  unsigned long long* Dg = reinterpret_cast<unsigned long long*>(S.Dg + dc.off + g0);
+  if (ns == 1) {
+    for (int i = threadIdx.x; i < ng; i += GJ_BLOCK) Dg[i] = acc[i];
+  } else {
+    for (int i = threadIdx.x; i < ng; i += GJ_BLOCK)
+      if (acc[i]) atomicAdd(&Dg[i], acc[i]);
   }
 }
 

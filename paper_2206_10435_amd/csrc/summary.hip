@@ -13,9 +13,17 @@
 //               offsets used by desummarization) and the group totals M
 // Downward (Sec. 3.5, Algorithms 3-4 condition each level on the levels
 // above): D_t(s) = sum over parent entries e' with value s in the joining
-// column of c_p(e') * D_p(e') * product of the other children's messages;
-// scattered with 64-bit atomics (exact: every partial sum is bounded by the
-// join size once the upward pass has not overflowed).
+// column of c_p(e') * D_p(e') * product of the other children's messages
+// (that product is recorded per entry and child by the upward pass).  Per
+// level, for children of at most DOWN_MAX_GROUPS groups:
+//   k_down_tile     a parent tile's items (group, term) ordered by bucket of
+//                   2^sh child groups in LDS, written in that order
+//   k_down_reduce   one bucket over a range of tiles summed per group in LDS,
+//                   written to D (or added, for buckets of several ranges)
+// and for larger children k_down scatters the terms with 64-bit atomics after
+// merging a tile's repeats in LDS.  Integer sums: exact in any order (every
+// partial sum is bounded by the join size once the upward pass has not
+// overflowed).
 // Compaction keeps entries with F = c*U*D > 0 and groups with M*D > 0 (Sec.
 // 3.3: entries of frequency below 1 are excluded) and re-links them.
 #include "gj_internal.h"
@@ -53,7 +61,19 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_up_scan(const WorkItem* __restrict
 __global__ void __launch_bounds__(GJ_BLOCK) k_down(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
                                                    FPtrs F, SPtrs S) {
   __shared__ __align__(16) unsigned char lds[LDS_DOWN];
-  down_body(wl[blockIdx.x], D, F, S, lds);
+  down_body<true>(wl[blockIdx.x], D, F, S, lds);
+}
+
+__global__ void __launch_bounds__(GJ_BLOCK) k_down_tile(const WorkItem* __restrict__ wl,
+                                                        const TDesc* __restrict__ D, FPtrs F, SPtrs S) {
+  __shared__ __align__(16) unsigned char lds[LDS_DTILE];
+  down_tile_body(wl[blockIdx.x], D, F, S, lds);
+}
+
+__global__ void __launch_bounds__(GJ_BLOCK) k_down_reduce(const WorkItem* __restrict__ wl,
+                                                          const TDesc* __restrict__ D, FPtrs F, SPtrs S) {
+  __shared__ __align__(16) unsigned char lds[LDS_DRED];
+  down_reduce_body(wl[blockIdx.x], D, F, S, lds);
 }
 
 __global__ void __launch_bounds__(GJ_BLOCK) k_compact_count(const WorkItem* __restrict__ wl,
@@ -109,8 +129,14 @@ void up_pass(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, in
   hipLaunchKernelGGL(k_up_scan, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
 }
 
-void down_pass(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F, const SPtrs& S) {
-  if (nwl > 0) hipLaunchKernelGGL(k_down, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
+void down_pass(hipStream_t s, const WorkItem* wl, int nwl, const WorkItem* rwl, int nrwl, bool bucketed,
+               bool scattered, const TDesc* D, const FPtrs& F, const SPtrs& S) {
+  if (nwl <= 0) return;
+  if (bucketed) {
+    hipLaunchKernelGGL(k_down_tile, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
+    if (nrwl > 0) hipLaunchKernelGGL(k_down_reduce, dim3(nrwl), dim3(GJ_BLOCK), 0, s, rwl, D, F, S);
+  }
+  if (scattered) hipLaunchKernelGGL(k_down, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, F, S);
 }
 
 void compact(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,

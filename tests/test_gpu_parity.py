@@ -297,3 +297,35 @@ def test_unroll_gfjs_fig1_and_ranges(gctx, oracle_mod):
         for (gv, gf), (ev, ef) in zip(got, exp):
             assert np.array_equal(gv, ev) and np.array_equal(gf, ef), (first, cnt)
             assert int(gf.sum()) == min(cnt, Q - first)
+
+
+def _bucketed_queries():
+    # parents with at least 4x their children's rows take the downward pass by
+    # buckets (child groups summed per bucket in LDS), the others the atomic
+    # scatter: star leaves of both kinds, small and large group counts (one
+    # group per bucket, and many), and a chain where a bucketed child's parent
+    # is itself a child (its downward message enters the items)
+    star = W.star_query(401, 0, 6, [60000, 200, 5000, 15000, 30000, 9000], 4000, 0.7, name="star_mixed")
+    skew = W.star_query(402, 0, 4, [70000, 3000, 17000, 1000], 600, 1.1, name="star_skewed")
+    chain = W.chain_query(403, 0, 4, [90000, 20000, 4000, 900], 3000, 0.5, name="chain_shrinking")
+    return [star, skew, chain]
+
+
+@pytest.mark.parametrize("q", _bucketed_queries(), ids=lambda q: q.name)
+def test_downward_pass_by_buckets(gctx, oracle_mod, q):
+    from paper_2206_10435_amd import gj
+
+    o = oracle_mod.Oracle(q)
+    Q, ovf = o.join_size()
+    _say("case bucketed down", q.name, "Q =", Q, "overflow", ovf)
+    assert not ovf
+    f = gctx.build_factors(gj.to_device_tables(q), q.parent, q.sep_col, q.parent_col)
+    s = gctx.summarize(f)
+    _summary_parity(s, o, q)
+    # the same summary from a batch of the query twice (one plan, both paths)
+    b = gctx.batch_create([dict(tables=gj.to_device_tables(q), parent=q.parent, sep_col=q.sep_col,
+                                parent_col=q.parent_col)] * 2)
+    b.launch(graph=True)
+    js, st = b.results()
+    assert list(js) == [Q, Q] and list(st) == [gj.GJ_OK, gj.GJ_OK]
+    _summary_parity(b.summary(1), o, q)
