@@ -871,6 +871,7 @@ static void desum_args(const gj_summary* s, int64_t first_row, int64_t nw, void*
     T.perm = s->f->F.perm + d.off;
     T.cpre = s->S.cpre + d.off;
     T.ccs = s->S.ccs + d.off;
+    T.cU = s->S.cU + d.off;
     T.crec = d.parent >= 0 ? s->S.crec + d.link_off : nullptr;
     T.parent = d.parent >= 0 ? d.parent - base : -1;
   }

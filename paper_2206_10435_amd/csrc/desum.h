@@ -10,6 +10,7 @@ struct DTab {
   const int64_t* cpre;     // surviving entry -> offset of its block inside its group (units of c*U)
   const int2* ccs;         // surviving entry -> (row count, first position in perm)
   const ChildRec* crec;    // (t >= 1) surviving parent entry -> this table's group
+  const int64_t* cU;       // surviving entry -> U (the group message is cpre + c*U at its last entry)
   int32_t parent;
 };
 
@@ -46,6 +47,7 @@ struct RunTab {
   const int64_t* cpre;    // surviving entry -> offset of its block inside its group (units of c*U)
   const int64_t* cc;      // surviving entry -> frequency c (int64)
   const ChildRec* crec;   // (t >= 1) surviving parent entry -> this table's group
+  const int64_t* cU;      // surviving entry -> U (the group message is cpre + c*U at its last entry)
   int32_t parent;
 };
 

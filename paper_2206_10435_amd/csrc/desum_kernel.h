@@ -189,10 +189,13 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
 #pragma unroll
         for (int j = t + 1; j < N; ++j) {
           if (j < n && a.tab[j].parent == t) {
-            const ChildRec rc = a.tab[j].crec[e[t]];
+            const gjk::DTab& C = a.tab[j];
+            const ChildRec rc = C.crec[e[t]];
             lo[j] = rc.first;
             gh[j] = rc.end;
-            mg[j] = (uint64_t)rc.M;
+            // the group's message: the block offset of its last entry plus that block
+            const int32_t x = rc.end - 1;
+            mg[j] = (uint64_t)C.cpre[x] + (uint64_t)C.ccs[x].x * (uint64_t)C.cU[x];
           }
         }
       }

@@ -70,10 +70,12 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_expand_runs(gjk::RunArgs a) {
 #pragma unroll
         for (int j = t + 1; j < N; ++j) {
           if (j < n && a.tab[j].parent == t) {
-            const ChildRec rc = a.tab[j].crec[x];
+            const gjk::RunTab& C = a.tab[j];
+            const ChildRec rc = C.crec[x];
             lo[j] = rc.first;
             gh[j] = rc.end;
-            mg[j] = (uint64_t)rc.M;
+            // the group's message: the block offset of its last entry plus that block
+            mg[j] = (uint64_t)C.cpre[rc.end - 1] + (uint64_t)C.cc[rc.end - 1] * (uint64_t)C.cU[rc.end - 1];
           }
         }
       }

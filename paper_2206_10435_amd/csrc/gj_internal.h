@@ -109,13 +109,12 @@ struct FPtrs {
 
 // Pointers of a plan's summary arrays.
 // What the expansion needs of a child table when its parent entry changes,
-// in one 32-byte record per (child table, surviving parent entry): the child's
-// group as a range [first, end) of its surviving entries, the row count and
-// first perm position of entry `first`, and the group's upward message M.
-struct __align__(32) ChildRec {
+// in one 16-byte record per (child table, surviving parent entry): the child's
+// group as a range [first, end) of its surviving entries, and the row count
+// and first perm position of entry `first`.  (The group's upward message M,
+// needed only to locate a rank, is cpre + c*U of the group's last entry.)
+struct __align__(16) ChildRec {
   int32_t first, end, c0, st0;
-  int64_t M;
-  int64_t unused;
 };
 
 struct SPtrs {

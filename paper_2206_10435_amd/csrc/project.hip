@@ -329,6 +329,7 @@ gj_status gj_desummarize_projected(gj_ctx* ctx, const gj_summary* s, int64_t fir
     gjk::RunTab& T = a.tab[t];
     T.cpre = s->S.cpre + d.off;
     T.cc = s->S.cc + d.off;
+    T.cU = s->S.cU + d.off;
     T.crec = d.parent >= 0 ? s->S.crec + d.link_off : nullptr;
     T.parent = d.parent >= 0 ? d.parent - base : -1;
   }

@@ -923,8 +923,6 @@ __device__ __forceinline__ void group_recs_body(const WorkItem w, const TDesc* _
     const int2 cs0 = rc.first < rc.end ? S.ccs[d.off + rc.first] : make_int2(0, 0);
     rc.c0 = cs0.x;
     rc.st0 = cs0.y;
-    rc.M = S.cgM[d.off + gc];
-    rc.unused = 0;
     S.grec[sg] = rc;
   }
 }

@@ -11,7 +11,7 @@
 //     keys     k x entries int32 (column-major)
 //     c, U, D, F, pre          entries int64 each
 //     s, M, D (edge, t >= 1)   groups int32, int64, int64
-//     child records (t >= 1)   entries(parent) x 32 bytes
+//     child records (t >= 1)   entries(parent) x 16 bytes (first, end, c0, st0 int32)
 //     with_rows: (count, first) entries x int2, then the grouped row ids rows x int32
 //
 // A reloaded summary answers the views, gj_desummarize_projected and (when
@@ -28,7 +28,7 @@ using namespace gjh;
 namespace {
 
 const char MAGIC[8] = {'G', 'J', 'S', 'U', 'M', 'M', '0', '1'};
-const int32_t VERSION = 1;
+const int32_t VERSION = 2;  // 2: 16-byte child records
 
 struct TabHdr {
   int32_t k, sep, pcol, parent, is_root;
@@ -81,7 +81,7 @@ gj_status file_to_dev(gj_ctx* ctx, FILE* f, T* dst, size_t bytes, std::vector<ch
 // lim[0]: entries of the child table
 bool crec_ok(const ChildRec* r, size_t n, const int64_t* lim) {
   for (size_t i = 0; i < n; ++i)
-    if (r[i].first < 0 || r[i].first > r[i].end || r[i].end > lim[0] || r[i].M < 0) return false;
+    if (r[i].first < 0 || r[i].first > r[i].end || r[i].end > lim[0]) return false;
   return true;
 }
 // lim[0]: rows of the table

@@ -5,9 +5,8 @@ magic "GJSUMM01"; int32 version, n_tables, projected, with_rows; int64 join
 size; per table int32 k, sep, pcol, parent, is_root (+4 bytes padding) and
 int64 entries, groups, rows; then per table its keys (column-major int32),
 c, U, D, F, pre (int64), for t >= 1 the edge's s (int32), M, D (int64) and
-one 32-byte child record (first, end, c0, st0 int32; M, unused int64) per
-parent entry, and with rows the (count, first) int32 pairs and the grouped
-row ids."""
+one 16-byte child record (first, end, c0, st0 int32) per parent entry, and
+with rows the (count, first) int32 pairs and the grouped row ids."""
 import struct
 
 import numpy as np
@@ -38,7 +37,7 @@ def sections(with_rows=True):
     for nm, v in (("c", [1, 1]), ("U", [1, 1]), ("D", [3, 3]), ("F", [3, 3]), ("pre", [0, 1])):
         out.append(("t1." + nm, _i64(v)))
     out += [("t1.s", _i32([5])), ("t1.M", _i64([2])), ("t1.Dg", _i64([3]))]
-    rec = b"".join(struct.pack("<4iqq", 0, 2, 1, 0, 2, 0) for _ in range(T0["entries"]))
+    rec = b"".join(struct.pack("<4i", 0, 2, 1, 0) for _ in range(T0["entries"]))
     out.append(("t1.crec", rec))
     if with_rows:
         out.insert(7, ("t0.ccs", _i32([1, 0, 2, 1])))
@@ -47,7 +46,10 @@ def sections(with_rows=True):
     return out
 
 
-def build(with_rows=True, tables=(T0, T1), join_size=6, version=1, magic=b"GJSUMM01", secs=None):
+VERSION = 2
+
+
+def build(with_rows=True, tables=(T0, T1), join_size=6, version=VERSION, magic=b"GJSUMM01", secs=None):
     b = HDR.pack(magic, version, len(tables), 0, 1 if with_rows else 0, join_size)
     for t in tables:
         b += TAB.pack(t["k"], t["sep"], t["pcol"], t["parent"], t["is_root"], t["entries"], t["groups"], t["rows"])
@@ -66,8 +68,9 @@ def damaged():
     bad = [
         ("empty file", b""),
         ("wrong magic", build(magic=b"GJSUMM02")),
-        ("wrong version", build(version=2)),
-        ("zero tables", HDR.pack(b"GJSUMM01", 1, 0, 0, 1, 6)),
+        ("older version (32-byte child records)", build(version=1)),
+        ("newer version", build(version=VERSION + 1)),
+        ("zero tables", HDR.pack(b"GJSUMM01", VERSION, 0, 0, 1, 6)),
         ("negative join size", build(join_size=-1)),
         ("truncated table headers", good[: HDR.size + TAB.size + 5]),
         ("truncated last section", good[:-3]),
@@ -79,9 +82,9 @@ def damaged():
         ("more entries than rows", build(tables=(dict(T0, entries=4), T1))),
         ("entry count 0", build(secs=_patch_section("t0.c", _i64([1, 0])))),
         ("child record past the child's entries",
-         build(secs=_patch_section("t1.crec", struct.pack("<4iqq", 0, 3, 1, 0, 2, 0) * 2))),
+         build(secs=_patch_section("t1.crec", struct.pack("<4i", 0, 3, 1, 0) * 2))),
         ("child record with first > end",
-         build(secs=_patch_section("t1.crec", struct.pack("<4iqq", 2, 1, 1, 0, 2, 0) * 2))),
+         build(secs=_patch_section("t1.crec", struct.pack("<4i", 2, 1, 1, 0) * 2))),
         ("row range past the table", build(secs=_patch_section("t0.ccs", _i32([1, 0, 2, 2])))),
         ("row id out of range", build(secs=_patch_section("t1.rows", _i32([1, 2])))),
     ]
