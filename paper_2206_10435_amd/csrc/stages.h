@@ -453,8 +453,9 @@ __device__ __forceinline__ void up_agg_body(const WorkItem w, const TDesc* __res
             U = smul(U, m);
           }
         }
-        // each child's product of the other children's messages (the
-        // downward pass multiplies it in instead of gathering them again)
+        // each child's product of the other children's messages, for the
+        // children summed by buckets in the downward pass (it multiplies the
+        // product in instead of gathering the messages again)
         {
           uint64_t pre = 1;
 #pragma unroll
@@ -464,7 +465,7 @@ __device__ __forceinline__ void up_agg_body(const WorkItem w, const TDesc* __res
 #pragma unroll
               for (int i2 = i + 1; i2 < MAXC; ++i2)
                 if (i2 < d.nchild) x = smul(x, mi[i2]);
-              S.xprod[D[d.child[i]].link_off + e] = (int64_t)x;
+              if (D[d.child[i]].dbucketed) S.xprod[D[d.child[i]].link_off + e] = (int64_t)x;
               pre = smul(pre, mi[i]);
             }
           }

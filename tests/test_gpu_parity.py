@@ -170,6 +170,12 @@ def test_wide_keys_128bit(gctx, oracle_mod):
     o = oracle_mod.Oracle(q)
     _say("case wide", o.join_size())
     _full(gctx, q, o)
+    try:
+        for si, rb in ((8, 5), (16, 7)):  # narrower digits on 128-bit words (more passes)
+            gctx.set_tune(si, rb)
+            _full(gctx, q, o)
+    finally:
+        gctx.set_tune()
 
 
 def test_degenerate_tables(gctx, oracle_mod):
