@@ -75,6 +75,12 @@ def test_roundtrip_with_rows(gctx, oracle_mod, tmp_path, qi):
     path = str(tmp_path / f"{q.name}.gjs")
     nb = gctx.save(s, path, with_rows=True)
     assert nb == os.path.getsize(path)
+    # the host-only check reads the same file back: header, entry and row counts
+    info = gj.summary_file_check(path)
+    assert info["bytes"] == nb and info["n_tables"] == q.n_tables and info["with_rows"]
+    assert info["join_size"] == s.join_size and not info["projected"]
+    assert info["entries"] == [len(s.table(t)["c"]) for t in range(q.n_tables)]
+    assert info["rows"] == [q.n_rows(t) for t in range(q.n_tables)]
     r = gctx.load(path)
     _say("case store", q.name, "bytes", nb, "Q", s.join_size)
     assert r.join_size == s.join_size == o.join_size()[0] and r.n_tables == q.n_tables
@@ -125,6 +131,8 @@ def test_roundtrip_without_rows_and_projected(gctx, oracle_mod, tmp_path):
         gctx.save(ps, str(tmp_path / "bad.gjs"), with_rows=True)
     pp = str(tmp_path / "proj.gjs")
     gctx.save(ps, pp, with_rows=False)
+    info = gj.summary_file_check(pp)
+    assert info["projected"] and not info["with_rows"] and info["n_tables"] == 2
     pr = gctx.load(pp)
     assert pr.n_tables == ps.n_tables == 2
     _same_views(ps, pr)
@@ -146,11 +154,15 @@ def test_damaged_files_refused(gctx, tmp_path):
         # the last table's last row id beyond the table
         "row id": data[:-4] + np.array([1 << 30], dtype=np.int32).tobytes(),
     }
+    cases["trailing"] = data + b"\0"
     for name, blob in cases.items():
         p = str(tmp_path / f"{name}.gjs")
         open(p, "wb").write(blob)
         with pytest.raises(gj.GJError) as ei:
             gctx.load(p)
+        assert ei.value.status == gj.GJ_E_INVALID, name
+        with pytest.raises(gj.GJError) as ei:
+            gj.summary_file_check(p)
         assert ei.value.status == gj.GJ_E_INVALID, name
     with pytest.raises(gj.GJError):
         gctx.load(str(tmp_path / "missing.gjs"))
