@@ -118,7 +118,11 @@ gj_status gj_validate(const gj_table* tables, const gj_join_graph* graph);
  * Builds every table's factor on the device.  Entries of the root are ordered
  * by its key columns in declared order; entries of any other table by its
  * separator column first, then its other columns in declared order; all
- * comparisons as signed int32.  Rows inside an entry ascend by row id. */
+ * comparisons as signed int32.  Rows inside an entry ascend by row id.  A
+ * table whose key columns' value ranges and row ids need more than 128 bits
+ * has its widest columns ranked among their distinct values for the sort
+ * (one more group-by per such column, with a host synchronization); it is
+ * refused (GJ_E_INVALID) only if ranks do not make it fit either. */
 gj_status gj_build_factors(gj_ctx* ctx, const gj_table* tables, const gj_join_graph* graph, gj_factors** out);
 
 /* View of table t's factor (device pointers valid while the factors live):

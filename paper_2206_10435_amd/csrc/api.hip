@@ -294,6 +294,71 @@ static gj_status pack_layout(Plan& P, int t, const int32_t* mm) {
   return GJ_OK;
 }
 
+// Tables whose key fields and row ids exceed a 128-bit sort word: their
+// widest columns are replaced by each row's rank among the column's distinct
+// values (ascending, so the order of key tuples is kept), found by the same
+// group-by run on that one column, until the key fits; the run writer maps
+// ranks back to values.  mm is updated to the ranks' range.
+static gj_status compress_wide_columns(Plan& P, Arena& A, std::vector<int32_t>& mm) {
+  hipStream_t s = P.ctx->stream;
+  for (int t = 0; t < P.nt; ++t) {
+    HTable& h = P.ht[t];
+    TDesc& d = P.td[t];
+    for (int c = 0; c < MAXK; ++c) d.vmap[c] = nullptr;
+    if (h.n <= 1) continue;
+    const int rb = bitwidth64((uint64_t)(h.n - 1));
+    int bits[MAXK] = {};
+    int total = 0;
+    for (int c = 0; c < h.k; ++c) {
+      bits[c] = bitwidth32((uint32_t)mm[(t * MAXK + c) * 2 + 1] - (uint32_t)mm[(t * MAXK + c) * 2]);
+      total += bits[c];
+    }
+    if (rb + total <= 128) continue;
+    std::vector<int> order(h.k), pick;
+    for (int c = 0; c < h.k; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return bits[a] > bits[b]; });
+    for (int c : order) {
+      if (rb + total <= 128) break;
+      if (bits[c] > rb) {  // a rank is below n, so it needs at most rb bits
+        total -= bits[c] - rb;
+        pick.push_back(c);
+      }
+    }
+    if (rb + total > 128) continue;  // pack_layout refuses the table
+    for (int c : pick) {
+      gj_factors sub(P.ctx);
+      sub.plan.ctx = P.ctx;
+      const int32_t* col = h.cols[c];
+      const gj_table tab{h.n, 1, &col};
+      const int32_t zero = 0, none = -1;
+      const gj_join_graph g{1, &none, &zero, &zero};
+      const int qoff[2] = {0, 1};
+      gj_status st;
+      if ((st = plan_tables(sub.plan, 1, qoff, &tab, &g)) || (st = plan_device(sub.plan, sub.arena, sub.F))) return st;
+      launch_factors(sub.plan, sub.F, s);
+      std::vector<int64_t> cnt;
+      if ((st = read_counters(sub.plan, sub.F, s, cnt))) return st;
+      const int64_t M = cnt[CNT_M];
+      int32_t* rank = A.get_n<int32_t>(h.n);
+      int32_t* vals = A.get_n<int32_t>(M);
+      if (!rank || !vals) return GJ_E_OOM;
+      const TDesc& sd = sub.plan.td[0];
+      if ((st = check(hipMemcpyAsync(vals, sub.F.ekey + sd.key_off, (size_t)M * 4, hipMemcpyDeviceToDevice, s),
+                      "column ranks")))
+        return st;
+      gjk::rank_rows(s, sub.F.perm + sd.off, sub.F.estart + sd.off, M, h.n, rank);
+      if ((st = check(hipGetLastError(), "column ranks")) || (st = check(hipStreamSynchronize(s), "column ranks")))
+        return st;
+      h.cols[c] = rank;
+      d.col[c] = rank;
+      d.vmap[c] = vals;
+      mm[(t * MAXK + c) * 2] = 0;
+      mm[(t * MAXK + c) * 2 + 1] = (int32_t)(M - 1);
+    }
+  }
+  return GJ_OK;
+}
+
 gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
   gj_ctx* ctx = P.ctx;
   hipStream_t s = ctx->stream;
@@ -329,6 +394,8 @@ gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
   std::vector<int32_t> mm((size_t)P.nt * MAXK * 2);
   if ((st = check(hipMemcpyAsync(mm.data(), d_mm, mm.size() * 4, hipMemcpyDeviceToHost, s), "key ranges"))) return st;
   if ((st = check(hipStreamSynchronize(s), "key ranges"))) return st;
+  const std::vector<int32_t> mm_values = mm;  // the columns' own ranges (separator indexes use them)
+  if ((st = compress_wide_columns(P, A, mm))) return st;
   // layout of the sort words
   int64_t woff = 0, hoff = 0;
   P.max_passes = 0;
@@ -352,7 +419,7 @@ gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
     d.drange = 0;
     d.dmin = 0;
     if (d.parent < 0 || d.n == 0) continue;
-    const int32_t lo = mm[(t * MAXK + d.sep) * 2], hi = mm[(t * MAXK + d.sep) * 2 + 1];
+    const int32_t lo = mm_values[(t * MAXK + d.sep) * 2], hi = mm_values[(t * MAXK + d.sep) * 2 + 1];
     const int64_t range = (int64_t)hi - (int64_t)lo + 1;
     if (range > 0 && range <= 4 * d.n + 4096 && range <= (1LL << 30)) {
       d.didx_off = P.didx_slots;

@@ -175,6 +175,23 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_entry_counts(const WorkItem* __res
   }
 }
 
+// rank[row] = the entry of the row's position, for the rows of a one-column
+// factor (entry e holds positions [estart[e], estart[e+1]) of perm).
+__global__ void k_rank_rows(const int32_t* __restrict__ perm, const int32_t* __restrict__ estart, int64_t m,
+                            int64_t n, int32_t* __restrict__ rank) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = m;  // the last entry starting at or before i
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (estart[mid] <= i)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    rank[perm[i]] = (int32_t)lo;
+  }
+}
+
 // One block per table (see tile_scan_pair_body).
 __global__ void __launch_bounds__(GJ_BLOCK) k_tile_scan_pair(const int32_t* __restrict__ tabs,
                                                              const TDesc* __restrict__ D, uint64_t* __restrict__ agg,
@@ -246,6 +263,12 @@ void runs_write(hipStream_t s, int wide, const WorkItem* wl, int nwl, const TDes
     hipLaunchKernelGGL(k_runs_write<1>, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, P.words[0], P.words[1], P.agg, P);
   else
     hipLaunchKernelGGL(k_runs_write<0>, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, P.words[0], P.words[1], P.agg, P);
+}
+
+void rank_rows(hipStream_t s, const int32_t* perm, const int32_t* estart, int64_t m, int64_t n, int32_t* rank) {
+  if (n <= 0 || m <= 0) return;
+  const int blocks = (int)std::min<int64_t>((n + GJ_BLOCK - 1) / GJ_BLOCK, 8192);
+  hipLaunchKernelGGL(k_rank_rows, dim3(blocks), dim3(GJ_BLOCK), 0, s, perm, estart, m, n, rank);
 }
 
 void group_index(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F) {

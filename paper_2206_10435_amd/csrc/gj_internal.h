@@ -47,6 +47,10 @@ struct TDesc {
   int32_t child[MAXC];
   int32_t child_col[MAXC];  // column of this table that child i joins on
   uint32_t kmin[MAXK];      // per declared column: minimum value (as uint32 of int32)
+  // per declared column: null, or the column's distinct values in ascending
+  // order when col[c] holds each row's rank among them (a column compressed
+  // so that the table's key fits the sort word; field f decodes to vmap[c][f])
+  const int32_t* vmap[MAXK];
   int32_t fshift[MAXK];     // per declared column: field position above the row-id bits
   int32_t fbits[MAXK];      // per declared column: field width
   int32_t rb;               // row-id bits (low bits of every sort word)

@@ -11,6 +11,8 @@ void fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v0, int32_t v1);
 void minmax(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,
             int32_t* mmt, int32_t* mm);
 void pack(hipStream_t s, int wide, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& P);
+// rank[perm[i]] = entry of position i of a one-column factor (m entries, n rows).
+void rank_rows(hipStream_t s, const int32_t* perm, const int32_t* estart, int64_t m, int64_t n, int32_t* rank);
 void radix_pass(hipStream_t s, int wide, int items, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab,
                 const TDesc* D, const FPtrs& P, int pass);
 void runs(hipStream_t s, int wide, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,

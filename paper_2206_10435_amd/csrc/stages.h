@@ -335,14 +335,14 @@ __device__ __forceinline__ void runs_write_body(const WorkItem w, const TDesc* _
       P.egrp[off + e] = (int32_t)g;
       for (int c = 0; c < d.k; ++c) {
         uint32_t f = field_of(word, d.rb + d.fshift[c], d.fbits[c]);
-        P.ekey[d.key_off + (int64_t)c * d.n + e] = (int32_t)(f + d.kmin[c]);
+        P.ekey[d.key_off + (int64_t)c * d.n + e] = d.vmap[c] ? d.vmap[c][f] : (int32_t)(f + d.kmin[c]);
       }
     }
     if (s) {
       P.glo[off + g] = (int32_t)e;
       int sc = d.is_root ? 0 : d.sep;
       uint32_t f = field_of(word, d.rb + d.fshift[sc], d.fbits[sc]);
-      P.gval[off + g] = (int32_t)(f + d.kmin[sc]);
+      P.gval[off + g] = d.vmap[sc] ? d.vmap[sc][f] : (int32_t)(f + d.kmin[sc]);
     }
     if (nh) P.eend[off + e] = (int32_t)(i + 1);
     if (ns) P.ghi[off + g] = (int32_t)(e + 1);

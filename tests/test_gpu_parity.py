@@ -178,6 +178,35 @@ def test_wide_keys_128bit(gctx, oracle_mod):
         gctx.set_tune()
 
 
+def _wide_keys_query():
+    # four full-range int32 key columns and a join column (more than 128 key
+    # bits with the row ids) in the root and in its child, some rows repeated
+    rng = np.random.default_rng(11)
+
+    def full(n):
+        return rng.integers(-2**31, 2**31 - 1, n, dtype=np.int64).astype(np.int32)
+
+    n0, n1, n2 = 9000, 4000, 2000
+    t0 = [full(n0) for _ in range(4)] + [rng.integers(0, 500, n0).astype(np.int32)]
+    t1 = [rng.integers(0, 500, n1).astype(np.int32)] + [full(n1) for _ in range(4)] + \
+         [rng.integers(0, 40, n1).astype(np.int32)]
+    t2 = [rng.integers(0, 40, n2).astype(np.int32), full(n2)]
+    for tab in (t0, t1):
+        for c in tab:
+            c[:150] = c[300:450]  # whole repeated rows: entries of count 2
+    t0[1][450:600] = t0[1][600:750]  # repeated values inside a column
+    return W.Query("wider_than_128", [t0, t1, t2], [-1, 0, 1], [0, 0, 0], [0, 4, 5])
+
+
+def test_keys_wider_than_a_sort_word(gctx, oracle_mod):
+    """Tables whose key and row-id bits exceed 128: the widest columns are
+    ranked for the sort and their values restored in the entries' keys."""
+    q = _wide_keys_query()
+    o = oracle_mod.Oracle(q)
+    _say("case wider than 128 bits", o.join_size())
+    _full(gctx, q, o, rowid_dtypes=("int32", "int64"))
+
+
 def test_degenerate_tables(gctx, oracle_mod):
     import torch
 
