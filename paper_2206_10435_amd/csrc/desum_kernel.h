@@ -162,40 +162,63 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum(gjk::DesumArgs a) {
     // ---- locate rank first + my0 ----
     uint64_t R = (uint64_t)(a.first + min(my0, a.n_rows - 1));
     uint64_t P = 1;
-    int32_t lo[N];
+    int32_t lo[N], fc[N], fs[N];
     uint64_t mg[N];
+    uint32_t have_mg = 0;  // bit j: mg[j] read
 #pragma unroll
     for (int t = 0; t < N; ++t) {
       lo[t] = 0;
       mg[t] = 1;
+      fc[t] = 1;
+      fs[t] = 0;
     }
     gh[0] = (int32_t)a.n_root;
 #pragma unroll
     for (int t = 0; t < N; ++t) {
       if (t < n) {
         const gjk::DTab& T = a.tab[t];
+        // The pending messages scale only a search over more than one entry:
+        // a group of one entry (a dimension joined on its key) needs neither
+        // them nor its block offset (0, the group's first) nor its count and
+        // start (in the child record), so its locate reads no random line.
         uint64_t Kt = P;
+        if (gh[t] - lo[t] > 1) {
 #pragma unroll
-        for (int j = t + 1; j < N; ++j)
-          if (j < n && a.tab[j].parent < t) Kt *= mg[j];
+          for (int j = t + 1; j < N; ++j) {
+            if (j < n && a.tab[j].parent < t) {
+              if (!((have_mg >> j) & 1)) {
+                // the group's message: the block offset of its last entry plus that block
+                const gjk::DTab& C = a.tab[j];
+                const int32_t x = gh[j] - 1;
+                mg[j] = (uint64_t)C.cpre[x] + (uint64_t)C.ccs[x].x * (uint64_t)C.cU[x];
+                have_mg |= 1u << j;
+              }
+              Kt *= mg[j];
+            }
+          }
+        }
         const int32_t x0 = find_block(T.cpre, lo[t], gh[t], Kt, R, ln);
         e[t] = x0;
-        R -= Kt * (uint64_t)T.cpre[x0];
-        const int2 cs = T.ccs[x0];
-        c[t] = cs.x;
-        st[t] = cs.y;
+        if (t == 0 || x0 != lo[t]) {
+          R -= Kt * (uint64_t)T.cpre[x0];
+          const int2 cs = T.ccs[x0];
+          c[t] = cs.x;
+          st[t] = cs.y;
+        } else {
+          c[t] = fc[t];
+          st[t] = fs[t];
+        }
         P *= (uint64_t)c[t];
-        // children: their group (entry range and message) under this entry
+        // children: their group (entry range, first entry's count and start)
+        // under this entry
 #pragma unroll
         for (int j = t + 1; j < N; ++j) {
           if (j < n && a.tab[j].parent == t) {
-            const gjk::DTab& C = a.tab[j];
-            const ChildRec rc = C.crec[e[t]];
-            lo[j] = rc.first;
-            gh[j] = rc.end;
-            // the group's message: the block offset of its last entry plus that block
-            const int32_t x = rc.end - 1;
-            mg[j] = (uint64_t)C.cpre[x] + (uint64_t)C.ccs[x].x * (uint64_t)C.cU[x];
+            const int4 rc = *reinterpret_cast<const int4*>(a.tab[j].crec + e[t]);
+            lo[j] = rc.x;
+            gh[j] = rc.y;
+            fc[j] = rc.z;
+            fs[j] = rc.w;
           }
         }
       }

@@ -48,6 +48,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_expand_runs(gjk::RunArgs a) {
     uint64_t P = 1;
     int32_t lo[N];
     uint64_t mg[N];
+    uint32_t have_mg = 0;  // bit j: mg[j] read
 #pragma unroll
     for (int t = 0; t < N; ++t) {
       lo[t] = 0;
@@ -58,24 +59,36 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_expand_runs(gjk::RunArgs a) {
     for (int t = 0; t < N; ++t) {
       if (t < n) {
         const gjk::RunTab& T = a.tab[t];
+        // pending messages only for a search over more than one entry, and
+        // no block offset for a group's first entry (0).  The frequency is
+        // read from cc: the record's 32-bit count cannot hold a projected one.
         uint64_t Kt = P;
+        if (gh[t] - lo[t] > 1) {
 #pragma unroll
-        for (int j = t + 1; j < N; ++j)
-          if (j < n && a.tab[j].parent < t) Kt *= mg[j];
+          for (int j = t + 1; j < N; ++j) {
+            if (j < n && a.tab[j].parent < t) {
+              if (!((have_mg >> j) & 1)) {
+                // the group's message: the block offset of its last entry plus that block
+                const gjk::RunTab& C = a.tab[j];
+                const int32_t y = gh[j] - 1;
+                mg[j] = (uint64_t)C.cpre[y] + (uint64_t)C.cc[y] * (uint64_t)C.cU[y];
+                have_mg |= 1u << j;
+              }
+              Kt *= mg[j];
+            }
+          }
+        }
         const int32_t x = find_block(T.cpre, lo[t], gh[t], Kt, R, ln);
         e[t] = x;
-        R -= Kt * (uint64_t)T.cpre[x];
+        if (x != lo[t]) R -= Kt * (uint64_t)T.cpre[x];
         c[t] = (uint64_t)T.cc[x];
         P *= c[t];
 #pragma unroll
         for (int j = t + 1; j < N; ++j) {
           if (j < n && a.tab[j].parent == t) {
-            const gjk::RunTab& C = a.tab[j];
-            const ChildRec rc = C.crec[x];
-            lo[j] = rc.first;
-            gh[j] = rc.end;
-            // the group's message: the block offset of its last entry plus that block
-            mg[j] = (uint64_t)C.cpre[rc.end - 1] + (uint64_t)C.cc[rc.end - 1] * (uint64_t)C.cU[rc.end - 1];
+            const int4 rc = *reinterpret_cast<const int4*>(a.tab[j].crec + x);
+            lo[j] = rc.x;
+            gh[j] = rc.y;
           }
         }
       }
