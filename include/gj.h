@@ -453,6 +453,9 @@ typedef struct {
   int32_t desum_stage;  /* tuples per lane per LDS staging round: 2, 4 or 8 */
   int32_t batch_task_rows; /* rows (or sort keys) per task of the persistent batch
                               kernel's plan (256..2^24), or 0: 16384 */
+  int32_t desum_general;   /* 0: gj_desummarize takes the keyed-lookup expansion for
+                              the summaries it applies to (gj_desum_kernel); 1: always
+                              the general expansion kernel (same result) */
 } gj_tune;
 gj_status gj_batch_create(gj_ctx* ctx, int32_t n_queries, const int32_t* q_off, const gj_table* tables,
                           const gj_join_graph* graphs, const gj_tune* tune, gj_batch** out);
@@ -499,6 +502,16 @@ typedef struct {
 } gj_desum_launch;
 gj_status gj_desum_launch_config(int32_t n_tables, int32_t rowid_bytes, int32_t n_cols, int64_t n_rows,
                                  const gj_tune* tune, gj_desum_launch* out);
+
+/* Which kernel gj_desummarize takes for summary s on this context: 1 for the
+ * keyed-lookup expansion, 0 for the general one (the result is the same).
+ * The keyed-lookup expansion (Sec. 3.6's order, decoded per rank) applies to
+ * row-id summaries of two or more tables in which every table other than the
+ * root and the innermost table holds exactly one surviving entry per
+ * surviving group (MC == GC in gj_summary_table), as a dimension joined on
+ * its key does; the context's tune can switch it off (desum_general).  Reads
+ * the summary's counts, which a batch summary fetches on first use. */
+gj_status gj_desum_kernel(gj_ctx* ctx, const gj_summary* s, int32_t* kind);
 
 /* Plumbing for bindings and tests: copies `bytes` of device memory to host
  * memory on the context stream and waits for it. */

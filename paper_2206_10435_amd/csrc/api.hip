@@ -655,6 +655,7 @@ gj_status gj_ctx_create(int device, void* hip_stream, gj_alloc_fn alloc, gj_free
   c->tune.desum_rounds = 0;
   c->tune.desum_stage = 4;
   c->tune.batch_task_rows = 0;
+  c->tune.desum_general = 0;
   *out = c;
   return GJ_OK;
 }
@@ -671,9 +672,9 @@ gj_status gj_ctx_set_tune(gj_ctx* ctx, const gj_tune* tune) {
   const int btr = tune->batch_task_rows;
   if ((tune->sort_items != 8 && tune->sort_items != 16) || tune->radix_bits < 4 || tune->radix_bits > 8 ||
       tune->desum_rounds < 0 || tune->desum_rounds > 1024 || !(stg == 2 || stg == 4 || stg == 8) ||
-      !(btr == 0 || (btr >= 256 && btr <= (1 << 24)))) {
+      !(btr == 0 || (btr >= 256 && btr <= (1 << 24))) || (tune->desum_general != 0 && tune->desum_general != 1)) {
     set_error("gj_ctx_set_tune: sort_items in {8,16}, radix_bits in [4,8], desum_rounds in [0,1024], "
-              "desum_stage in {2,4,8}, batch_task_rows 0 or in [256, 2^24]");
+              "desum_stage in {2,4,8}, batch_task_rows 0 or in [256, 2^24], desum_general 0 or 1");
     return GJ_E_INVALID;
   }
   ctx->tune = *tune;
@@ -948,7 +949,35 @@ static void desum_args(const gj_summary* s, int64_t first_row, int64_t nw, void*
   a.out = out;
 }
 
+// The keyed-lookup expansion applies when every table strictly between the
+// root and the innermost one has one surviving entry per surviving group: a
+// surviving group has at least one surviving entry (its message is positive
+// and the entries' groups survive with it), so equal counts mean exactly one.
+static bool unit_expansion(const gj_ctx* ctx, const gj_summary* s) {
+  if (ctx->tune.desum_general || s->projected || !s->f->F.perm) return false;
+  const Plan& P = s->f->plan;
+  const int base = P.qfirst[s->query];
+  const int n = P.qfirst[s->query + 1] - base;
+  if (n < 2) return false;
+  for (int t = 1; t < n - 1; ++t) {
+    const int64_t* c = &s->cnt_host[(size_t)(base + t) * CNT_STRIDE];
+    if (c[CNT_MC] != c[CNT_GC]) return false;
+  }
+  return true;
+}
+
 extern "C" {
+
+gj_status gj_desum_kernel(gj_ctx* ctx, const gj_summary* s, int32_t* kind) {
+  GJ_SCOPE(ctx);
+  if (!ctx || !s || !kind) {
+    set_error("gj_desum_kernel: null argument");
+    return GJ_E_INVALID;
+  }
+  if (gj_status st = summary_host(s)) return st;
+  *kind = unit_expansion(ctx, s) ? 1 : 0;
+  return GJ_OK;
+}
 
 gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, int64_t n_rows, int32_t rowid_bytes,
                          void* out, int64_t* n_written) {
@@ -976,7 +1005,10 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
   gjk::DesumArgs a{};
   desum_args(s, first_row, nw, out, a, n);
   if (nw > 0) {
-    if (gjk::desummarize(ctx->stream, a, rowid_bytes, n, ctx->tune.desum_rounds, ctx->tune.desum_stage) != 0) {
+    const int rc = unit_expansion(ctx, s) ? gjk::desummarize_unit(ctx->stream, a, rowid_bytes, n)
+                                     : gjk::desummarize(ctx->stream, a, rowid_bytes, n, ctx->tune.desum_rounds,
+                                                        ctx->tune.desum_stage);
+    if (rc != 0) {
       set_error("gj_desummarize: chunk too large for one launch");
       return GJ_E_INVALID;
     }

@@ -56,6 +56,10 @@ struct DesumPlan {
 DesumPlan desum_plan(int n_tables, int rowid_bytes, int n_cols, int64_t n_rows, int rounds_per_lane, int stage);
 // returns -1 if the launch does not fit one grid
 int desummarize(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables, int rounds_per_lane, int stage);
+// Row-id expansion of a summary whose middle tables hold one entry per group
+// (desum_unit.hip); 0 on success, -1 for unsupported arguments.
+int desummarize_unit(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables);
+int64_t desum_unit_blocks(int64_t n_rows);
 // value columns (desum_values.hip): tuples per staging round, and the launch
 int value_round(int n_tables, int n_cols);
 void launch_values(hipStream_t s, const DesumArgs& a, int blocks);

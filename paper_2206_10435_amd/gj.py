@@ -71,7 +71,7 @@ class _PotView(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("sort_items", C.c_int32), ("radix_bits", C.c_int32), ("desum_rounds", C.c_int32),
-                ("desum_stage", C.c_int32), ("batch_task_rows", C.c_int32)]
+                ("desum_stage", C.c_int32), ("batch_task_rows", C.c_int32), ("desum_general", C.c_int32)]
 
 
 class SummaryFileInfo(C.Structure):
@@ -127,6 +127,7 @@ SIGNATURES = {
     "gj_download": (C.c_int, [_vp, _vp, _vp, _sz]),
     "gj_ctx_set_tune": (C.c_int, [_vp, _vp]),
     "gj_desum_launch_config": (C.c_int, [_i32, _i32, _i32, _i64, _vp, _vp]),
+    "gj_desum_kernel": (C.c_int, [_vp, _vp, _vp]),
     "gj_colset_create": (C.c_int, [_vp, _vp, _i32, _vp, _vp, _vp]),
     "gj_free_colset": (None, [_vp]),
     "gj_desummarize_values": (C.c_int, [_vp, _vp, _vp, _i64, _i64, _vp, _vp]),
@@ -298,9 +299,16 @@ class Context:
             self.L.gj_ctx_destroy(self.h)
             self.h = None
 
-    def set_tune(self, sort_items=8, radix_bits=8, desum_rounds=0, desum_stage=4, batch_task_rows=0):
-        t = Tune(sort_items, radix_bits, desum_rounds, desum_stage, batch_task_rows)
+    def set_tune(self, sort_items=8, radix_bits=8, desum_rounds=0, desum_stage=4, batch_task_rows=0,
+                 desum_general=0):
+        t = Tune(sort_items, radix_bits, desum_rounds, desum_stage, batch_task_rows, desum_general)
         self._check(self.L.gj_ctx_set_tune(self.h, C.byref(t)))
+
+    def desum_kernel(self, s: "Summary") -> str:
+        """'unit' when desummarize takes the keyed-lookup expansion for s, else 'general'."""
+        k = C.c_int32(-1)
+        self._check(self.L.gj_desum_kernel(self.h, s.h, C.byref(k)))
+        return "unit" if k.value == 1 else "general"
 
     def download(self, ptr: int, n: int, dtype) -> np.ndarray:
         out = np.empty(max(n, 0), dtype=dtype)

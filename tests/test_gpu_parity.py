@@ -283,7 +283,9 @@ def test_expansion_every_stage_width_table_count(gctx, oracle_mod, q):
     try:
         for stage in (2, 4, 8):
             for rounds in (1, 7):
-                gctx.set_tune(16, 8, rounds, stage)
+                # the general kernel (a two-table summary would take the keyed-lookup one)
+                gctx.set_tune(16, 8, rounds, stage, desum_general=1)
+                assert gctx.desum_kernel(s) == "general"
                 for dt in (torch.int32, torch.int64):
                     got, nw = _desum(gctx, s, n, 0, Q, dt)
                     assert nw == Q and np.array_equal(got, ref), (stage, rounds, dt)

@@ -1,0 +1,158 @@
+"""The keyed-lookup expansion -- row-id desummarization of summaries whose
+tables between the root and the innermost table hold one entry per group --
+against the oracle's canonical result (Definition 1's order) and against the
+general expansion kernel on the same summary, bit-exact: stars of dimensions
+joined on their keys with a bridge below one of them (the star-plus-chain
+shape at small sizes), repeated fact rows (root counts above 1), duplicated
+dimension rows (middle counts above 1), innermost groups of several entries,
+chains with a keyed middle table, two-table joins, and one-tuple root blocks
+(every window of 64 ranks spans 64 root entries); int32 and int64 row ids,
+whole results and ragged windows."""
+import numpy as np
+import pytest
+
+from paper_2206_10435_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gctx():
+    from paper_2206_10435_amd import gj
+
+    return gj.Context(0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _star(seed, fact, dims, bridge_rows, bridge_dom, s, dup_fact=0, dup_dim=0, bridge_extra=0, bridge=True):
+    """Fact F(k1..kd) uniform into dimensions D_i(pk[, j]) (pk a permutation);
+    D1.j and a bridge B(j[, x]) Zipf(s) over bridge_dom, B a child of D1.
+    dup_fact repeats fact rows (root entries of count 2), dup_dim repeats rows
+    of the last dimension (its single entries get count 2), bridge_extra > 0
+    adds a bridge column x over that many values (several entries per group)."""
+    rng = np.random.default_rng(seed)
+    fcols = [rng.integers(0, nd, size=fact).astype(np.int32) for nd in dims]
+    if dup_fact:
+        idx = rng.integers(0, fact, size=dup_fact)
+        fcols = [np.concatenate([c, c[idx]]) for c in fcols]
+    tables = [fcols]
+    for i, nd in enumerate(dims):
+        pk = rng.permutation(nd).astype(np.int32)
+        cols = [pk]
+        if i == 0 and bridge:
+            cols.append(W.zipf_ranks(rng, s, bridge_dom, nd).astype(np.int32))
+        if i == len(dims) - 1 and dup_dim:
+            idx = rng.integers(0, nd, size=dup_dim)
+            cols = [np.concatenate([c, c[idx]]) for c in cols]
+        tables.append(cols)
+    parent = [-1] + [0] * len(dims)
+    sep = [0] * (len(dims) + 1)
+    pcol = [0] + list(range(len(dims)))
+    if bridge:
+        bcols = [W.zipf_ranks(rng, s, bridge_dom, bridge_rows).astype(np.int32)]
+        if bridge_extra:
+            bcols.append(rng.integers(0, bridge_extra, size=bridge_rows).astype(np.int32))
+        tables.append(bcols)
+        parent.append(1)
+        sep.append(0)
+        pcol.append(1)
+    name = f"star{len(dims)}_s{seed}" + ("_bridge" if bridge else "")
+    return W.Query(name, tables, parent, sep, pcol)
+
+
+def _chain_keyed_middle(seed, n_a, n_b, n_c, dom_c, s):
+    """A(x, y) -> B(y, z) with y a key of B -> C(z, w): B's groups hold one entry."""
+    rng = np.random.default_rng(seed)
+    a = [rng.integers(0, 50, size=n_a).astype(np.int32), rng.integers(0, n_b, size=n_a).astype(np.int32)]
+    b = [rng.permutation(n_b).astype(np.int32), W.zipf_ranks(rng, s, dom_c, n_b).astype(np.int32)]
+    c = [W.zipf_ranks(rng, s, dom_c, n_c).astype(np.int32), rng.integers(0, 7, size=n_c).astype(np.int32)]
+    return W.Query(f"chain3_keyed_s{seed}", [a, b, c], [-1, 0, 1], [0, 0, 0], [0, 1, 1])
+
+
+def _one_tuple_blocks(seed, n):
+    """R(a) -> S(a), both permutations: every root entry expands to one tuple."""
+    rng = np.random.default_rng(seed)
+    r = [rng.permutation(n).astype(np.int32)]
+    t = [rng.permutation(n).astype(np.int32), rng.integers(0, 3, size=n).astype(np.int32)]
+    return W.Query(f"pair_unit_blocks_{n}", [r, t], [-1, 0], [0, 0], [0, 0])
+
+
+def _two_table(seed, n_r, n_s, dom, s):
+    rng = np.random.default_rng(seed)
+    r = [W.zipf_ranks(rng, s, dom, n_r).astype(np.int32), rng.integers(0, 5, size=n_r).astype(np.int32)]
+    t = [W.zipf_ranks(rng, s, dom, n_s).astype(np.int32), rng.integers(0, 9, size=n_s).astype(np.int32)]
+    return W.Query(f"pair_zipf_s{seed}", [r, t], [-1, 0], [0, 0], [0, 0])
+
+
+def _cases():
+    return [
+        _star(1, 20000, (400, 60, 150, 250), 3000, 400, 0.9),
+        _star(2, 15000, (300, 40, 90, 120), 2500, 300, 0.9, dup_fact=3000),
+        _star(3, 12000, (300, 40, 90, 120), 2000, 300, 0.7, dup_dim=40),
+        _star(4, 12000, (300, 40, 90, 120), 2500, 300, 0.9, bridge_extra=6),
+        _star(5, 9000, (200, 30, 80, 100), 2000, 200, 0.9, dup_fact=2000, dup_dim=30, bridge_extra=4),
+        _star(6, 30000, (500, 70, 200), 0, 0, 0.0, bridge=False),
+        _chain_keyed_middle(7, 6000, 900, 4000, 300, 0.8),
+        _one_tuple_blocks(8, 70001),
+        _two_table(9, 5000, 4000, 600, 1.0),
+    ]
+
+
+def _desum(gctx, s, n, first, count, dtype):
+    import torch
+
+    out = torch.full((max(count, 1) * n,), -7, dtype=dtype, device="cuda:0")
+    nw = gctx.desummarize(s, first, count, out)
+    assert nw == count
+    return out[: nw * n].view(nw, n).cpu().numpy().astype(np.int64)
+
+
+@pytest.mark.parametrize("q", _cases(), ids=lambda q: q.name)
+def test_keyed_lookup_expansion_matches_oracle(gctx, oracle_mod, q):
+    import torch
+
+    from paper_2206_10435_amd import gj
+
+    o = oracle_mod.Oracle(q)
+    Q, ovf = o.join_size()
+    assert not ovf and 0 < Q <= 4_000_000, Q
+    _say("case unit", q.name, "Q =", Q)
+    ref = o.canonical_result().astype(np.int64)
+    s = gctx.summarize(gctx.build_factors(gj.to_device_tables(q), q.parent, q.sep_col, q.parent_col))
+    assert s.join_size == Q
+    n = q.n_tables
+    assert gctx.desum_kernel(s) == "unit"
+    windows = [(0, Q), (1, min(63, Q - 1)), (64, min(65, Q - 64)), (Q // 3 + 5, min(4097 + 7, Q - Q // 3 - 5)),
+               (Q - 100, 100), (Q - 1, 1), (Q, 0)]
+    for dt in (torch.int32, torch.int64):
+        for first, cnt in windows:
+            got = _desum(gctx, s, n, first, cnt, dt)
+            assert np.array_equal(got, ref[first:first + cnt]), (dt, first, cnt)
+    # the general kernel on the same summary: the same tuples
+    try:
+        gctx.set_tune(desum_general=1)
+        assert gctx.desum_kernel(s) == "general"
+        got = _desum(gctx, s, n, 0, Q, torch.int64)
+        assert np.array_equal(got, ref)
+    finally:
+        gctx.set_tune()
+    assert gctx.desum_kernel(s) == "unit"
+
+
+def test_kernel_choice_follows_the_middle_tables(gctx, oracle_mod):
+    """A chain whose middle table has groups of several entries takes the
+    general kernel; a one-table query too (no innermost table below a root)."""
+    from paper_2206_10435_amd import gj
+
+    q = W.chain_query(31, 0, 3, 3000, 200, 0.8, name="chain3_general")
+    s = gctx.summarize(gctx.build_factors(gj.to_device_tables(q), q.parent, q.sep_col, q.parent_col))
+    mc = s.table(1)["keys"].shape[0]
+    groups = len(np.unique(s.table(1)["keys"][:, q.sep_col[1]]))
+    assert mc > groups  # some group of the middle table holds several entries
+    assert gctx.desum_kernel(s) == "general"
+    q1 = W.Query("single", [[np.arange(100, dtype=np.int32) % 7]], [-1], [0], [0])
+    s1 = gctx.summarize(gctx.build_factors(gj.to_device_tables(q1), q1.parent, q1.sep_col, q1.parent_col))
+    assert gctx.desum_kernel(s1) == "general"
