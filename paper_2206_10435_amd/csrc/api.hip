@@ -1005,9 +1005,30 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
   gjk::DesumArgs a{};
   desum_args(s, first_row, nw, out, a, n);
   if (nw > 0) {
-    const int rc = unit_expansion(ctx, s) ? gjk::desummarize_unit(ctx->stream, a, rowid_bytes, n)
-                                     : gjk::desummarize(ctx->stream, a, rowid_bytes, n, ctx->tune.desum_rounds,
-                                                        ctx->tune.desum_stage);
+    int rc;
+    if (unit_expansion(ctx, s)) {
+      // the root entries' records, when they are small against the output
+      // (stream-ordered scratch, released on return)
+      Arena A(ctx);
+      int64_t cap = gjk::desum_unit_record_entries(a.n_root, nw, n, rowid_bytes);
+      int64_t* range = nullptr;
+      int32_t* rec = nullptr;
+      if (cap > 0) {
+        range = A.get_n<int64_t>(2);
+        rec = range ? reinterpret_cast<int32_t*>(A.get(gjk::desum_unit_record_bytes(cap, n))) : nullptr;
+        if (!rec) {
+          // no room for the records: they are decoded in place (and the
+          // failed allocation is not reported as the launch's error)
+          (void)hipGetLastError();
+          set_error("%s", "");
+          range = nullptr;
+          cap = 0;
+        }
+      }
+      rc = gjk::desummarize_unit(ctx->stream, a, rowid_bytes, n, range, rec, cap);
+    } else {
+      rc = gjk::desummarize(ctx->stream, a, rowid_bytes, n, ctx->tune.desum_rounds, ctx->tune.desum_stage);
+    }
     if (rc != 0) {
       set_error("gj_desummarize: chunk too large for one launch");
       return GJ_E_INVALID;

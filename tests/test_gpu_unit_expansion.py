@@ -6,8 +6,10 @@ joined on their keys with a bridge below one of them (the star-plus-chain
 shape at small sizes), repeated fact rows (root counts above 1), duplicated
 dimension rows (middle counts above 1), innermost groups of several entries,
 chains with a keyed middle table, two-table joins, and one-tuple root blocks
-(every window of 64 ranks spans 64 root entries); int32 and int64 row ids,
-whole results and ragged windows."""
+(every window of 64 ranks spans 64 root entries), alone and next to long
+blocks; int32 and int64 row ids, whole results and ragged windows.  Whole
+results of the larger cases take the record pass (root-entry records written
+first); the one-tuple case and the short windows decode records in place."""
 import numpy as np
 import pytest
 
@@ -80,6 +82,20 @@ def _one_tuple_blocks(seed, n):
     return W.Query(f"pair_unit_blocks_{n}", [r, t], [-1, 0], [0, 0], [0, 0])
 
 
+def _mixed_blocks(seed, n):
+    """R(a) -> S(a): the first half of R's keys match one row of S, the rest 40
+    rows each; the records of R's entries stay small against the output, so
+    the expansion takes them from the record pass while runs of 64 one-tuple
+    entries fill whole windows."""
+    rng = np.random.default_rng(seed)
+    r = [rng.permutation(n).astype(np.int32)]
+    half = n // 2
+    keys = np.concatenate([np.arange(half), np.repeat(np.arange(half, n), 40)])
+    rng.shuffle(keys)
+    t = [keys.astype(np.int32), rng.integers(0, 1000, size=len(keys)).astype(np.int32)]
+    return W.Query(f"pair_mixed_blocks_{n}", [r, t], [-1, 0], [0, 0], [0, 0])
+
+
 def _two_table(seed, n_r, n_s, dom, s):
     rng = np.random.default_rng(seed)
     r = [W.zipf_ranks(rng, s, dom, n_r).astype(np.int32), rng.integers(0, 5, size=n_r).astype(np.int32)]
@@ -97,6 +113,7 @@ def _cases():
         _star(6, 30000, (500, 70, 200), 0, 0, 0.0, bridge=False),
         _chain_keyed_middle(7, 6000, 900, 4000, 300, 0.8),
         _one_tuple_blocks(8, 70001),
+        _mixed_blocks(10, 10000),
         _two_table(9, 5000, 4000, 600, 1.0),
     ]
 
