@@ -13,8 +13,11 @@ size is about 2e12; 16 chunks (4.3e9 tuples, 137 GB of row ids) are written
 per step.
 
 Prints one JSON line.  `value` = tuples materialized per second of whole-step
-time; the roofline object is for the expansion kernel (HIP events around each
-launch on the stream the kernel runs on).  The line also carries, unless
+time; the roofline object is for the expansion (HIP events around each
+expansion call of a full chunk, on the stream its kernels run on: the general
+kernel, or for summaries whose middle tables hold one entry per group, as in
+the star workload, the keyed-lookup form's record pass and expansion;
+`expand_kernel` names which).  The line also carries, unless
 --no-legs: `weighted` (every row's gradient of the weighted join size by one
 adjoint pass against one re-rooted forward pass per table, with the largest
 relative difference) and `batch` (256 queries as one recorded graph of
@@ -477,6 +480,7 @@ def main():
         ft = autotune.tune_factors(ctx, tabs, q.parent, q.sep_col, q.parent_col)
         dt = autotune.tune_desummarize(ctx, s, out, 0, chunk_rows[0], ft["sort_items"], ft["radix_bits"])
         tune_rec = autotune.apply(ctx, ft, dt)
+    expand_kernel = ctx.desum_kernel(s)  # "unit": the keyed-lookup expansion (record pass + expansion)
     del f, s
     torch.cuda.synchronize()
 
@@ -557,6 +561,7 @@ def main():
         },
         "summary_build_rows_per_s": total_rows / build_avg,
         "summary_build_ms": build_avg * 1000.0,
+        "expand_kernel": expand_kernel,
         "expand_kernel_ms": avg_ms,
         "write_ceiling_GBps": fill_gbps,
         "roofline": {
