@@ -219,7 +219,11 @@ void gj_free_summary(gj_summary* s);
  * table -- ties broken by the row ids (r_0, .., r_{n-1})) as row-major
  * [n_rows x n_tables] row ids of `rowid_bytes` (4: int32, 8: int64) each into
  * device buffer `out`.  Rows past the join size are not written; *n_written
- * (host) receives the count.  first_row > join size -> GJ_E_RANGE. */
+ * (host) receives the count.  first_row > join size -> GJ_E_RANGE.  For
+ * summaries whose middle tables hold one entry per group (gj_desum_kernel)
+ * the call may take stream-ordered scratch from the context's allocator for
+ * root-entry records (at most a quarter of the output bytes, released before
+ * it returns); if that allocation fails the records are decoded in place. */
 gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, int64_t n_rows, int32_t rowid_bytes,
                          void* out, int64_t* n_written);
 
