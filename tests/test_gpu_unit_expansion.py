@@ -173,3 +173,52 @@ def test_kernel_choice_follows_the_middle_tables(gctx, oracle_mod):
     q1 = W.Query("single", [[np.arange(100, dtype=np.int32) % 7]], [-1], [0], [0])
     s1 = gctx.summarize(gctx.build_factors(gj.to_device_tables(q1), q1.parent, q1.sep_col, q1.parent_col))
     assert gctx.desum_kernel(s1) == "general"
+
+
+def test_records_decoded_in_place_when_scratch_is_refused(oracle_mod):
+    """The record pass takes scratch from the context's allocator; when the
+    allocator refuses it, the expansion decodes the records in place and the
+    result is the same, with nothing left allocated."""
+    import gc
+
+    import torch
+
+    from paper_2206_10435_amd import gj
+
+    state = {"refuse": False, "live": set(), "refused": 0}
+    stream = torch.cuda.current_stream()
+
+    def alloc(nbytes):
+        if state["refuse"]:
+            state["refused"] += 1
+            return 0
+        p = torch.cuda.caching_allocator_alloc(nbytes, 0, stream)
+        state["live"].add(p)
+        return p
+
+    def free(p):
+        state["live"].discard(p)
+        torch.cuda.caching_allocator_delete(p)
+
+    ctx = gj.Context(0, allocator=(alloc, free))
+    q = _star(11, 20000, (400, 60, 150, 250), 3000, 400, 0.9)
+    o = oracle_mod.Oracle(q)
+    ref = o.canonical_result().astype(np.int64)
+    s = ctx.summarize(ctx.build_factors(gj.to_device_tables(q), q.parent, q.sep_col, q.parent_col))
+    Q = s.join_size
+    assert Q == len(ref) and ctx.desum_kernel(s) == "unit"
+    _say("case refused scratch", q.name, "Q =", Q)
+    live_before = set(state["live"])
+    for refuse in (False, True):
+        state["refuse"] = refuse
+        out = torch.full((Q * q.n_tables,), -7, dtype=torch.int64, device="cuda:0")
+        assert ctx.desummarize(s, 0, Q, out) == Q
+        got = out.view(Q, q.n_tables).cpu().numpy()
+        assert np.array_equal(got, ref), refuse
+        assert state["live"] == live_before, refuse  # the scratch went back
+    assert state["refused"] >= 1  # the record pass asked and was refused
+    state["refuse"] = False
+    del s
+    gc.collect()
+    torch.cuda.synchronize()
+    assert not state["live"]
