@@ -1010,12 +1010,15 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
       // the root entries' records, when they are small against the output
       // (stream-ordered scratch, released on return)
       Arena A(ctx);
-      int64_t cap = gjk::desum_unit_record_entries(a.n_root, nw, n, rowid_bytes);
+      // the innermost table with one entry per group as well: no entry range per record
+      const int64_t* ct = &s->cnt_host[(size_t)(s->f->plan.qfirst[s->query] + n - 1) * CNT_STRIDE];
+      const bool tl_single = ct[CNT_MC] == ct[CNT_GC];
+      int64_t cap = gjk::desum_unit_record_entries(a.n_root, nw, n, rowid_bytes, tl_single);
       int64_t* range = nullptr;
       int32_t* rec = nullptr;
       if (cap > 0) {
         range = A.get_n<int64_t>(2);
-        rec = range ? reinterpret_cast<int32_t*>(A.get(gjk::desum_unit_record_bytes(cap, n))) : nullptr;
+        rec = range ? reinterpret_cast<int32_t*>(A.get(gjk::desum_unit_record_bytes(cap, n, tl_single))) : nullptr;
         if (!rec) {
           // no room for the records: they are decoded in place (and the
           // failed allocation is not reported as the launch's error)
@@ -1025,7 +1028,7 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
           cap = 0;
         }
       }
-      rc = gjk::desummarize_unit(ctx->stream, a, rowid_bytes, n, range, rec, cap);
+      rc = gjk::desummarize_unit(ctx->stream, a, rowid_bytes, n, tl_single, range, rec, cap);
     } else {
       rc = gjk::desummarize(ctx->stream, a, rowid_bytes, n, ctx->tune.desum_rounds, ctx->tune.desum_stage);
     }

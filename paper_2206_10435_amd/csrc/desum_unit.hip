@@ -41,25 +41,32 @@ namespace {
 
 constexpr int UNIT_WAVE_TUPLES = 4096;  // tuples per wavefront (one cooperative locate each)
 
-// Fields of a root entry's record, int32 each.
+// Fields of a root entry's record, int32 each.  When the innermost table too
+// holds one entry per group (TS), its group is that entry alone and the range
+// fields are left out.
 enum : int {
   F_C0 = 0,  // row count, negated when a middle count is above 1
   F_ST0,     // first position in the root's perm
-  F_GF,      // innermost group: first surviving entry
-  F_GE,      // one past its last
-  F_GC,      // count of its first entry
+  F_GC,      // innermost group: count of its first entry
   F_GST,     // perm start of its first entry
-  F_MID      // row ids of the middle tables 1 .. n-2
+  F_GF,      // first surviving entry (not with TS)
+  F_GE       // one past its last (not with TS)
 };
+// first field of the middle tables' row ids (tables 1 .. n-2)
+constexpr int f_mid(bool ts) { return ts ? 4 : 6; }
+constexpr int n_fields(int n, bool ts) { return f_mid(ts) + n - 2; }
 
 // LDS of one wavefront of the expansion: 64 records, their block offsets, the
 // window's entry-start marks and one window of tuples.
-constexpr int unit_wave_lds(int N, int wbytes) { return 64 * (F_MID + N - 2) * 4 + 64 * 8 + 64 + 64 * N * wbytes; }
+constexpr int unit_wave_lds(int N, int wbytes, bool ts) {
+  return 64 * n_fields(N, ts) * 4 + 64 * 8 + 64 + 64 * N * wbytes;
+}
 
-// The record of root entry x (fields as above, f[F_MID + t - 1] for middle
+// The record of root entry x (fields as above, f[f_mid(TS) + t - 1] for middle
 // table t).
-template <int N, bool NT = false>
-__device__ __forceinline__ void decode_entry(const gjk::DesumArgs& a, int n, int32_t x, int32_t (&f)[F_MID + N - 2]) {
+template <int N, bool TS, bool NT = false>
+__device__ __forceinline__ void decode_entry(const gjk::DesumArgs& a, int n, int32_t x, int32_t (&f)[n_fields(N, TS)]) {
+  constexpr int FM = f_mid(TS);
   const int tl = n - 1;
   typedef int v4i __attribute__((ext_vector_type(4)));
   int2 cs;
@@ -111,12 +118,14 @@ __device__ __forceinline__ void decode_entry(const gjk::DesumArgs& a, int n, int
   }
   f[F_C0] = big ? -cs.x : cs.x;
   f[F_ST0] = cs.y;
-  f[F_GF] = gf;
-  f[F_GE] = ge;
   f[F_GC] = gc;
   f[F_GST] = gst;
+  if constexpr (!TS) {
+    f[F_GF] = gf;
+    f[F_GE] = ge;
+  }
 #pragma unroll
-  for (int t = 1; t < N - 1; ++t) f[F_MID + t - 1] = t < tl ? a.tab[t].perm[pos[t]] : 0;
+  for (int t = 1; t < N - 1; ++t) f[FM + t - 1] = t < tl ? a.tab[t].perm[pos[t]] : 0;
 }
 
 // range[0], range[1]: the root entries of the chunk's first and last ranks
@@ -134,28 +143,29 @@ __global__ void __launch_bounds__(64) k_unit_range(gjk::DesumArgs a, int64_t* __
 
 // Records of root entries range[0] .. range[1], field f of entry range[0] + i
 // at rec[f * cap + i].
-template <int N>
+template <int N, bool TS>
 __global__ void __launch_bounds__(GJ_BLOCK) k_unit_records(gjk::DesumArgs a, const int64_t* __restrict__ range,
                                                            int32_t* __restrict__ rec, int64_t cap) {
-  constexpr int NF = F_MID + N - 2;
+  constexpr int NF = n_fields(N, TS);
   const int n = N <= 8 ? N : a.n_tables;
   const int64_t i = (int64_t)blockIdx.x * GJ_BLOCK + threadIdx.x;
   const int64_t e0 = range[0];
   if (i > range[1] - e0 || i >= cap) return;
   int32_t f[NF];
-  decode_entry<N, true>(a, n, (int32_t)(e0 + i), f);
+  decode_entry<N, TS, true>(a, n, (int32_t)(e0 + i), f);
 #pragma unroll
   for (int k = 0; k < NF; ++k)
-    if (k < F_MID + n - 2) __builtin_nontemporal_store(f[k], rec + k * cap + i);
+    if (k < n_fields(n, TS)) __builtin_nontemporal_store(f[k], rec + k * cap + i);
 }
 
-template <int N, typename WT, bool REC>
+template <int N, typename WT, bool REC, bool TS>
 __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const int64_t* __restrict__ range,
                                                          const int32_t* __restrict__ rec, int64_t cap) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  constexpr int NF = F_MID + N - 2;  // fields of a record
+  constexpr int NF = n_fields(N, TS);  // fields of a record
+  constexpr int FM = f_mid(TS);
   const int n = N <= 8 ? N : a.n_tables;
-  const int nf = F_MID + n - 2;
+  const int nf = n_fields(n, TS);
   const int tl = n - 1;  // innermost table, a leaf
   const int ln = lane_id();
   // XCD-aware order: consecutive wave ranges on the same XCD
@@ -166,7 +176,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const
   if (w0 >= a.n_rows) return;  // wave-uniform
   const int64_t w1 = min(a.n_rows, w0 + (int64_t)UNIT_WAVE_TUPLES);
   const int tb = n * (int)sizeof(WT);  // tuple bytes
-  unsigned char* wl = lds_raw + (int64_t)wave_id() * unit_wave_lds(N, (int)sizeof(WT));
+  unsigned char* wl = lds_raw + (int64_t)wave_id() * unit_wave_lds(N, (int)sizeof(WT), TS);
   int32_t* tab = reinterpret_cast<int32_t*>(wl);                      // records, [field * 64 + lane]
   uint64_t* toff = reinterpret_cast<uint64_t*>(wl + 64 * NF * 4);     // their block offsets
   unsigned char* mark = wl + 64 * NF * 4 + 64 * 8;                    // entry starts in a window
@@ -199,7 +209,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const
 #pragma unroll
       for (int k = 0; k < NF; ++k) f[k] = k < nf ? rp[k * cap] : 0;
     } else {
-      decode_entry<N>(a, n, x, f);
+      decode_entry<N, TS>(a, n, x, f);
     }
     // every read of the previous records precedes this point in the wave's
     // program order
@@ -308,13 +318,13 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const
     const uint64_t R1 = Rw + (uint64_t)li - vj;
     const int32_t c0 = g[F_C0];
     const int32_t st0 = g[F_ST0];
-    const int32_t gf = g[F_GF];
-    const int32_t ge = g[F_GE];
+    const int32_t gf = TS ? 0 : g[F_GF];
+    const int32_t ge = TS ? 1 : g[F_GE];
     int32_t c = g[F_GC];
     int32_t st = g[F_GST];
     int32_t rid[N];
 #pragma unroll
-    for (int t = 0; t < N; ++t) rid[t] = (t >= 1 && t < tl) ? g[F_MID + t - 1] : 0;
+    for (int t = 0; t < N; ++t) rid[t] = (t >= 1 && t < tl) ? g[FM + t - 1] : 0;
 
     // ---- innermost entry inside its group, the row indexes ----
     const gjk::DTab& T = a.tab[tl];
@@ -352,7 +362,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const
       }
     }
     uint64_t R2 = R1;
-    if (__any(ge - gf > 1)) {
+    if (!TS && __any(ge - gf > 1)) {
       const int32_t x = find_block(T.cpre, gf, ge, P, R1, ln);
       if (x != gf) {
         R2 -= P * (uint64_t)T.cpre[x];
@@ -423,24 +433,37 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const
   }
 }
 
-template <int N>
+template <int N, bool TS>
 void launch_unit(hipStream_t s, const gjk::DesumArgs& a, int rowid_bytes, int blocks, int64_t* range, int32_t* rec,
                  int64_t cap) {
-  const size_t lds = (size_t)GJ_WAVES * unit_wave_lds(N, rowid_bytes);
+  const size_t lds = (size_t)GJ_WAVES * unit_wave_lds(N, rowid_bytes, TS);
   if (rec) {
     hipLaunchKernelGGL(k_unit_range, dim3(1), dim3(64), 0, s, a, range);
     const int64_t rb = (cap + GJ_BLOCK - 1) / GJ_BLOCK;
-    hipLaunchKernelGGL((k_unit_records<N>), dim3((unsigned)rb), dim3(GJ_BLOCK), 0, s, a, range, rec, cap);
+    hipLaunchKernelGGL((k_unit_records<N, TS>), dim3((unsigned)rb), dim3(GJ_BLOCK), 0, s, a, range, rec, cap);
     if (rowid_bytes == 4)
-      hipLaunchKernelGGL((k_desum_unit<N, int32_t, true>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec, cap);
+      hipLaunchKernelGGL((k_desum_unit<N, int32_t, true, TS>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec,
+                         cap);
     else
-      hipLaunchKernelGGL((k_desum_unit<N, int64_t, true>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec, cap);
+      hipLaunchKernelGGL((k_desum_unit<N, int64_t, true, TS>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec,
+                         cap);
   } else {
     if (rowid_bytes == 4)
-      hipLaunchKernelGGL((k_desum_unit<N, int32_t, false>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec, cap);
+      hipLaunchKernelGGL((k_desum_unit<N, int32_t, false, TS>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec,
+                         cap);
     else
-      hipLaunchKernelGGL((k_desum_unit<N, int64_t, false>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec, cap);
+      hipLaunchKernelGGL((k_desum_unit<N, int64_t, false, TS>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec,
+                         cap);
   }
+}
+
+template <int N>
+void launch_unit_ts(hipStream_t s, const gjk::DesumArgs& a, int rowid_bytes, int blocks, int64_t* range, int32_t* rec,
+                    int64_t cap, bool tl_single) {
+  if (tl_single)
+    launch_unit<N, true>(s, a, rowid_bytes, blocks, range, rec, cap);
+  else
+    launch_unit<N, false>(s, a, rowid_bytes, blocks, range, rec, cap);
 }
 
 }  // namespace
@@ -453,18 +476,20 @@ int64_t desum_unit_blocks(int64_t n_rows) {
   return (blocks + 7) / 8 * 8;  // whole XCD rounds for the block remap
 }
 
-int64_t desum_unit_record_entries(int64_t n_root, int64_t n_rows, int n_tables, int rowid_bytes) {
+int64_t desum_unit_record_bytes(int64_t cap, int n_tables, bool tl_single) {
+  return cap * (int64_t)n_fields(n_tables, tl_single) * 4;
+}
+
+int64_t desum_unit_record_entries(int64_t n_root, int64_t n_rows, int n_tables, int rowid_bytes, bool tl_single) {
   // the chunk's ranks span at most min(n_root, n_rows) root entries; records
   // only when they take at most a quarter of the chunk's output bytes
   const int64_t cap = std::min(n_root, n_rows);
-  const int64_t rec_bytes = cap * (int64_t)(F_MID + n_tables - 2) * 4;
+  const int64_t rec_bytes = desum_unit_record_bytes(cap, n_tables, tl_single);
   return rec_bytes * 4 <= n_rows * (int64_t)n_tables * rowid_bytes ? cap : 0;
 }
 
-int64_t desum_unit_record_bytes(int64_t cap, int n_tables) { return cap * (int64_t)(F_MID + n_tables - 2) * 4; }
-
-int desummarize_unit(hipStream_t s, const DesumArgs& a0, int rowid_bytes, int n_tables, int64_t* range, int32_t* rec,
-                     int64_t cap) {
+int desummarize_unit(hipStream_t s, const DesumArgs& a0, int rowid_bytes, int n_tables, bool tl_single, int64_t* range,
+                     int32_t* rec, int64_t cap) {
   if (a0.n_rows <= 0) return 0;
   if (n_tables < 2 || n_tables > GJ_MAX_TABLES || (rowid_bytes != 4 && rowid_bytes != 8) || a0.n_cols != 0 ||
       (rec && (!range || cap < std::min(a0.n_root, a0.n_rows))))
@@ -473,15 +498,16 @@ int desummarize_unit(hipStream_t s, const DesumArgs& a0, int rowid_bytes, int n_
   if (blocks > 0x7fffffff || (rec && (cap + GJ_BLOCK - 1) / GJ_BLOCK > 0x7fffffff)) return -1;
   DesumArgs a = a0;
   a.n_tables = n_tables;
+  const int nb = (int)blocks;
   switch (n_tables) {
-    case 2: launch_unit<2>(s, a, rowid_bytes, (int)blocks, range, rec, cap); break;
-    case 3: launch_unit<3>(s, a, rowid_bytes, (int)blocks, range, rec, cap); break;
-    case 4: launch_unit<4>(s, a, rowid_bytes, (int)blocks, range, rec, cap); break;
-    case 5: launch_unit<5>(s, a, rowid_bytes, (int)blocks, range, rec, cap); break;
-    case 6: launch_unit<6>(s, a, rowid_bytes, (int)blocks, range, rec, cap); break;
-    case 7: launch_unit<7>(s, a, rowid_bytes, (int)blocks, range, rec, cap); break;
-    case 8: launch_unit<8>(s, a, rowid_bytes, (int)blocks, range, rec, cap); break;
-    default: launch_unit<GJ_MAX_TABLES>(s, a, rowid_bytes, (int)blocks, range, rec, cap); break;
+    case 2: launch_unit_ts<2>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 3: launch_unit_ts<3>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 4: launch_unit_ts<4>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 5: launch_unit_ts<5>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 6: launch_unit_ts<6>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 7: launch_unit_ts<7>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 8: launch_unit_ts<8>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    default: launch_unit_ts<GJ_MAX_TABLES>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
   }
   return 0;
 }

@@ -57,15 +57,16 @@ DesumPlan desum_plan(int n_tables, int rowid_bytes, int n_cols, int64_t n_rows, 
 // returns -1 if the launch does not fit one grid
 int desummarize(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables, int rounds_per_lane, int stage);
 // Row-id expansion of a summary whose middle tables hold one entry per group
-// (desum_unit.hip); 0 on success, -1 for unsupported arguments.  With `rec`
-// (int32, desum_unit_record_bytes of `cap` entries, cap from
+// (desum_unit.hip); 0 on success, -1 for unsupported arguments.  tl_single:
+// the innermost table holds one entry per group too.  With `rec` (int32,
+// desum_unit_record_bytes of `cap` entries, cap from
 // desum_unit_record_entries) and `range` (2 int64) the root entries' records
 // are written by a pass of their own first; rec = nullptr decodes them in place.
-int desummarize_unit(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables, int64_t* range, int32_t* rec,
-                     int64_t cap);
+int desummarize_unit(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables, bool tl_single, int64_t* range,
+                     int32_t* rec, int64_t cap);
 int64_t desum_unit_blocks(int64_t n_rows);
-int64_t desum_unit_record_entries(int64_t n_root, int64_t n_rows, int n_tables, int rowid_bytes);
-int64_t desum_unit_record_bytes(int64_t cap, int n_tables);
+int64_t desum_unit_record_entries(int64_t n_root, int64_t n_rows, int n_tables, int rowid_bytes, bool tl_single);
+int64_t desum_unit_record_bytes(int64_t cap, int n_tables, bool tl_single);
 // value columns (desum_values.hip): tuples per staging round, and the launch
 int value_round(int n_tables, int n_cols);
 void launch_values(hipStream_t s, const DesumArgs& a, int blocks);
