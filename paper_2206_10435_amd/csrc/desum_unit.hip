@@ -46,7 +46,7 @@ constexpr int UNIT_WAVE_TUPLES = 4096;  // tuples per wavefront (one cooperative
 // fields are left out.
 enum : int {
   F_C0 = 0,  // row count, negated when a middle count is above 1
-  F_ST0,     // first position in the root's perm
+  F_ST0,     // first position in the root's perm; its row id when the count is 1
   F_GC,      // innermost group: count of its first entry
   F_GST,     // perm start of its first entry
   F_GF,      // first surviving entry (not with TS)
@@ -117,7 +117,8 @@ __device__ __forceinline__ void decode_entry(const gjk::DesumArgs& a, int n, int
     }
   }
   f[F_C0] = big ? -cs.x : cs.x;
-  f[F_ST0] = cs.y;
+  // one row and no middle count above 1: the root's row index is always 0
+  f[F_ST0] = (cs.x == 1 && !big) ? a.tab[0].perm[cs.y] : cs.y;
   f[F_GC] = gc;
   f[F_GST] = gst;
   if constexpr (!TS) {
@@ -397,8 +398,9 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const
         }
       }
     }
-    // the gathers: the root's row and the innermost table's
-    rid[0] = a.tab[0].perm[st0 + (int32_t)q];
+    // the gathers: the root's row (held in the record for a one-row entry)
+    // and the innermost table's
+    rid[0] = c0 == 1 ? st0 : a.tab[0].perm[st0 + (int32_t)q];
     rid[tl] = T.perm[st + (int32_t)rt];
 
     // ---- the window through the wave's LDS ----
