@@ -115,6 +115,9 @@ def _cases():
         _one_tuple_blocks(8, 70001),
         _mixed_blocks(10, 10000),
         _two_table(9, 5000, 4000, 600, 1.0),
+        # eight tables (the largest exact instance) and nine (the instance for any count)
+        _star(12, 8000, (100, 30, 40, 50, 60, 70), 1500, 100, 0.8, bridge_extra=3),
+        _star(13, 8000, (100, 30, 40, 50, 60, 70, 80), 1500, 100, 0.8),
     ]
 
 
