@@ -966,6 +966,34 @@ static bool unit_expansion(const gj_ctx* ctx, const gj_summary* s) {
   return true;
 }
 
+// The keyed-lookup expansion of a (row ids, or a.n_cols value columns): the
+// root entries' records first when they are small against the output
+// (stream-ordered scratch, released on return), else decoded in place.
+static int run_unit_expansion(gj_ctx* ctx, const gj_summary* s, const gjk::DesumArgs& a, int n, int rowid_bytes) {
+  Arena A(ctx);
+  // the innermost table with one entry per group as well: no entry range per record
+  const int64_t* ct = &s->cnt_host[(size_t)(s->f->plan.qfirst[s->query] + n - 1) * CNT_STRIDE];
+  const bool tl_single = ct[CNT_MC] == ct[CNT_GC];
+  const int tuple_bytes = a.n_cols > 0 ? a.n_cols * 4 : n * rowid_bytes;
+  int64_t cap = gjk::desum_unit_record_entries(a.n_root, a.n_rows, n, tl_single, a.n_cols, tuple_bytes);
+  int64_t* range = nullptr;
+  int32_t* rec = nullptr;
+  if (cap > 0) {
+    range = A.get_n<int64_t>(2);
+    rec = range ? reinterpret_cast<int32_t*>(A.get(gjk::desum_unit_record_bytes(cap, n, tl_single, a.n_cols)))
+                : nullptr;
+    if (!rec) {
+      // no room for the records: they are decoded in place (and the failed
+      // allocation is not reported as the launch's error)
+      (void)hipGetLastError();
+      set_error("%s", "");
+      range = nullptr;
+      cap = 0;
+    }
+  }
+  return gjk::desummarize_unit(ctx->stream, a, rowid_bytes, n, tl_single, range, rec, cap);
+}
+
 extern "C" {
 
 gj_status gj_desum_kernel(gj_ctx* ctx, const gj_summary* s, int32_t* kind) {
@@ -1007,28 +1035,7 @@ gj_status gj_desummarize(gj_ctx* ctx, const gj_summary* s, int64_t first_row, in
   if (nw > 0) {
     int rc;
     if (unit_expansion(ctx, s)) {
-      // the root entries' records, when they are small against the output
-      // (stream-ordered scratch, released on return)
-      Arena A(ctx);
-      // the innermost table with one entry per group as well: no entry range per record
-      const int64_t* ct = &s->cnt_host[(size_t)(s->f->plan.qfirst[s->query] + n - 1) * CNT_STRIDE];
-      const bool tl_single = ct[CNT_MC] == ct[CNT_GC];
-      int64_t cap = gjk::desum_unit_record_entries(a.n_root, nw, n, rowid_bytes, tl_single);
-      int64_t* range = nullptr;
-      int32_t* rec = nullptr;
-      if (cap > 0) {
-        range = A.get_n<int64_t>(2);
-        rec = range ? reinterpret_cast<int32_t*>(A.get(gjk::desum_unit_record_bytes(cap, n, tl_single))) : nullptr;
-        if (!rec) {
-          // no room for the records: they are decoded in place (and the
-          // failed allocation is not reported as the launch's error)
-          (void)hipGetLastError();
-          set_error("%s", "");
-          range = nullptr;
-          cap = 0;
-        }
-      }
-      rc = gjk::desummarize_unit(ctx->stream, a, rowid_bytes, n, tl_single, range, rec, cap);
+      rc = run_unit_expansion(ctx, s, a, n, rowid_bytes);
     } else {
       rc = gjk::desummarize(ctx->stream, a, rowid_bytes, n, ctx->tune.desum_rounds, ctx->tune.desum_stage);
     }
@@ -1128,7 +1135,10 @@ gj_status gj_desummarize_values(gj_ctx* ctx, const gj_summary* s, const gj_colse
     a.col_src[j] = cs->col[j];
   }
   if (nw > 0) {
-    if (gjk::desummarize(ctx->stream, a, 4, n, ctx->tune.desum_rounds, ctx->tune.desum_stage) != 0) {
+    const int rc = unit_expansion(ctx, s)
+                       ? run_unit_expansion(ctx, s, a, n, 4)
+                       : gjk::desummarize(ctx->stream, a, 4, n, ctx->tune.desum_rounds, ctx->tune.desum_stage);
+    if (rc != 0) {
       set_error("gj_desummarize_values: chunk too large for one launch");
       return GJ_E_INVALID;
     }

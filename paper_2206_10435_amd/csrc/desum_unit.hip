@@ -52,20 +52,21 @@ enum : int {
   F_GF,      // first surviving entry (not with TS)
   F_GE       // one past its last (not with TS)
 };
-// first field of the middle tables' row ids (tables 1 .. n-2)
+// First field after the fixed ones: the middle tables' row ids (tables 1 ..
+// n-2), or with value columns one slot per output column (its value when its
+// table is a middle table, or the root's for a root entry of one row).
 constexpr int f_mid(bool ts) { return ts ? 4 : 6; }
-constexpr int n_fields(int n, bool ts) { return f_mid(ts) + n - 2; }
+constexpr int n_fields(int n, bool ts, int n_cols) { return f_mid(ts) + (n_cols > 0 ? n_cols : n - 2); }
 
-// LDS of one wavefront of the expansion: 64 records, their block offsets, the
-// window's entry-start marks and one window of tuples.
-constexpr int unit_wave_lds(int N, int wbytes, bool ts) {
-  return 64 * n_fields(N, ts) * 4 + 64 * 8 + 64 + 64 * N * wbytes;
-}
+// LDS of one wavefront of the expansion: 64 records of nf fields, their block
+// offsets, the window's entry-start marks and one window of tuples.
+constexpr int unit_wave_lds(int nf, int tuple_bytes) { return 64 * nf * 4 + 64 * 8 + 64 + 64 * tuple_bytes; }
 
-// The record of root entry x (fields as above, f[f_mid(TS) + t - 1] for middle
-// table t).
-template <int N, bool TS, bool NT = false>
-__device__ __forceinline__ void decode_entry(const gjk::DesumArgs& a, int n, int32_t x, int32_t (&f)[n_fields(N, TS)]) {
+// The record of root entry x (fields as above; f[f_mid(TS) + t - 1] for middle
+// table t, or with value columns (NC > 0) f[f_mid(TS) + j] for column j).
+template <int N, bool TS, int NC, bool NT = false>
+__device__ __forceinline__ void decode_entry(const gjk::DesumArgs& a, int n, int32_t x,
+                                             int32_t (&f)[n_fields(N, TS, NC)]) {
   constexpr int FM = f_mid(TS);
   const int tl = n - 1;
   typedef int v4i __attribute__((ext_vector_type(4)));
@@ -118,15 +119,33 @@ __device__ __forceinline__ void decode_entry(const gjk::DesumArgs& a, int n, int
   }
   f[F_C0] = big ? -cs.x : cs.x;
   // one row and no middle count above 1: the root's row index is always 0
-  f[F_ST0] = (cs.x == 1 && !big) ? a.tab[0].perm[cs.y] : cs.y;
+  const bool one = cs.x == 1 && !big;
   f[F_GC] = gc;
   f[F_GST] = gst;
   if constexpr (!TS) {
     f[F_GF] = gf;
     f[F_GE] = ge;
   }
+  if constexpr (NC == 0) {
+    f[F_ST0] = one ? a.tab[0].perm[cs.y] : cs.y;
 #pragma unroll
-  for (int t = 1; t < N - 1; ++t) f[FM + t - 1] = t < tl ? a.tab[t].perm[pos[t]] : 0;
+    for (int t = 1; t < N - 1; ++t) f[FM + t - 1] = t < tl ? a.tab[t].perm[pos[t]] : 0;
+  } else {
+    f[F_ST0] = cs.y;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      int32_t val = 0;
+      if (j < a.n_cols) {
+        const int tj = a.col_tab[j];
+        int32_t pj = cs.y;  // the root's first row
+#pragma unroll
+        for (int t = 1; t < N; ++t)
+          if (t == tj) pj = pos[t];
+        if ((tj >= 1 && tj < tl) || (tj == 0 && one)) val = a.col_src[j][pj];
+      }
+      f[FM + j] = val;
+    }
+  }
 }
 
 // range[0], range[1]: the root entries of the chunk's first and last ranks
@@ -144,29 +163,36 @@ __global__ void __launch_bounds__(64) k_unit_range(gjk::DesumArgs a, int64_t* __
 
 // Records of root entries range[0] .. range[1], field f of entry range[0] + i
 // at rec[f * cap + i].
-template <int N, bool TS>
+template <int N, bool TS, int NC>
 __global__ void __launch_bounds__(GJ_BLOCK) k_unit_records(gjk::DesumArgs a, const int64_t* __restrict__ range,
                                                            int32_t* __restrict__ rec, int64_t cap) {
-  constexpr int NF = n_fields(N, TS);
-  const int n = N <= 8 ? N : a.n_tables;
+  constexpr int NF = n_fields(N, TS, NC);
+  const int n = (N <= 8 && NC == 0) ? N : a.n_tables;
+  const int nf = n_fields(n, TS, NC == 0 ? 0 : a.n_cols);
   const int64_t i = (int64_t)blockIdx.x * GJ_BLOCK + threadIdx.x;
   const int64_t e0 = range[0];
   if (i > range[1] - e0 || i >= cap) return;
   int32_t f[NF];
-  decode_entry<N, TS, true>(a, n, (int32_t)(e0 + i), f);
+  decode_entry<N, TS, NC, true>(a, n, (int32_t)(e0 + i), f);
 #pragma unroll
   for (int k = 0; k < NF; ++k)
-    if (k < n_fields(n, TS)) __builtin_nontemporal_store(f[k], rec + k * cap + i);
+    if (k < nf) __builtin_nontemporal_store(f[k], rec + k * cap + i);
 }
 
-template <int N, typename WT, bool REC, bool TS>
+// NC == 0: the output columns are the row ids of the n tables (N <= 8 is the
+// exact table count).  NC > 0: the output columns are a.n_cols <= NC int32
+// value columns, column j read from a.col_src[j] at the group position of
+// table a.col_tab[j]; N is then an upper bound of the table count.
+template <int N, typename WT, bool REC, bool TS, int NC>
 __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const int64_t* __restrict__ range,
                                                          const int32_t* __restrict__ rec, int64_t cap) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  constexpr int NF = n_fields(N, TS);  // fields of a record
+  constexpr int NF = n_fields(N, TS, NC);  // fields of a record
   constexpr int FM = f_mid(TS);
-  const int n = N <= 8 ? N : a.n_tables;
-  const int nf = n_fields(n, TS);
+  constexpr int NCOL = NC == 0 ? N : NC;  // register capacity for output columns
+  const int n = (N <= 8 && NC == 0) ? N : a.n_tables;
+  const int nc = NC == 0 ? n : a.n_cols;
+  const int nf = n_fields(n, TS, NC == 0 ? 0 : nc);
   const int tl = n - 1;  // innermost table, a leaf
   const int ln = lane_id();
   // XCD-aware order: consecutive wave ranges on the same XCD
@@ -176,8 +202,8 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const
   const int64_t w0 = ((int64_t)lb * GJ_WAVES + wave_id()) * UNIT_WAVE_TUPLES;
   if (w0 >= a.n_rows) return;  // wave-uniform
   const int64_t w1 = min(a.n_rows, w0 + (int64_t)UNIT_WAVE_TUPLES);
-  const int tb = n * (int)sizeof(WT);  // tuple bytes
-  unsigned char* wl = lds_raw + (int64_t)wave_id() * unit_wave_lds(N, (int)sizeof(WT), TS);
+  const int tb = nc * (int)sizeof(WT);  // tuple bytes
+  unsigned char* wl = lds_raw + (int64_t)wave_id() * unit_wave_lds(NF, NCOL * (int)sizeof(WT));
   int32_t* tab = reinterpret_cast<int32_t*>(wl);                      // records, [field * 64 + lane]
   uint64_t* toff = reinterpret_cast<uint64_t*>(wl + 64 * NF * 4);     // their block offsets
   unsigned char* mark = wl + 64 * NF * 4 + 64 * 8;                    // entry starts in a window
@@ -210,7 +236,7 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const
 #pragma unroll
       for (int k = 0; k < NF; ++k) f[k] = k < nf ? rp[k * cap] : 0;
     } else {
-      decode_entry<N, TS>(a, n, x, f);
+      decode_entry<N, TS, NC>(a, n, x, f);
     }
     // every read of the previous records precedes this point in the wave's
     // program order
@@ -323,9 +349,6 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const
     const int32_t ge = TS ? 1 : g[F_GE];
     int32_t c = g[F_GC];
     int32_t st = g[F_GST];
-    int32_t rid[N];
-#pragma unroll
-    for (int t = 0; t < N; ++t) rid[t] = (t >= 1 && t < tl) ? g[FM + t - 1] : 0;
 
     // ---- innermost entry inside its group, the row indexes ----
     const gjk::DTab& T = a.tab[tl];
@@ -333,11 +356,12 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const
     // P: the product of the counts above the innermost table; with a middle
     // count above 1 (rare) the middle tables' child records are read again
     uint64_t P = (uint32_t)(big ? -c0 : c0);
-    int32_t cm[N], pm[N];  // middle counts and perm starts (big only)
+    int32_t cm[N], pm[N], rm[N];  // middle counts, perm starts and row indexes (big only)
 #pragma unroll
     for (int t = 0; t < N; ++t) {
       cm[t] = 1;
       pm[t] = 0;
+      rm[t] = 0;
     }
     if (__any(big)) {
       if (big) {
@@ -391,24 +415,55 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const
         for (int t = N - 1; t >= 1; --t) {
           if (t < tl) {
             const uint64_t qt = q / (uint64_t)cm[t];
-            const int32_t r = (int32_t)(q - qt * (uint64_t)cm[t]);
+            rm[t] = (int32_t)(q - qt * (uint64_t)cm[t]);
             q = qt;
-            if (r != 0) rid[t] = a.tab[t].perm[pm[t] + r];
           }
         }
       }
     }
-    // the gathers: the root's row (held in the record for a one-row entry)
-    // and the innermost table's
-    rid[0] = c0 == 1 ? st0 : a.tab[0].perm[st0 + (int32_t)q];
-    rid[tl] = T.perm[st + (int32_t)rt];
+    // the gathers: the root's and the innermost table's rows (the root's held
+    // in the record for a one-row entry), a middle table's only when its row
+    // index is not 0
+    int32_t rid[NCOL];
+    if constexpr (NC == 0) {
+#pragma unroll
+      for (int t = 0; t < N; ++t) {
+        rid[t] = 0;
+        if (t >= 1 && t < tl) rid[t] = rm[t] != 0 ? a.tab[t].perm[pm[t] + rm[t]] : g[FM + t - 1];
+      }
+      rid[0] = c0 == 1 ? st0 : a.tab[0].perm[st0 + (int32_t)q];
+      rid[tl] = T.perm[st + (int32_t)rt];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        rid[j] = 0;
+        if (j < nc) {
+          const int tj = a.col_tab[j];
+          const int32_t* src = a.col_src[j];
+          if (tj == tl) {
+            rid[j] = src[st + (int32_t)rt];
+          } else if (tj == 0) {
+            rid[j] = c0 == 1 ? g[FM + j] : src[st0 + (int32_t)q];
+          } else {
+            int32_t r = 0, p = 0;
+#pragma unroll
+            for (int t = 1; t < N; ++t)
+              if (t == tj) {
+                r = rm[t];
+                p = pm[t];
+              }
+            rid[j] = r != 0 ? src[p + r] : g[FM + j];
+          }
+        }
+      }
+    }
 
     // ---- the window through the wave's LDS ----
     const int nv = (int)min((int64_t)64, w1 - t0);
     WT* my = reinterpret_cast<WT*>(stage + ln * tb);
 #pragma unroll
-    for (int t = 0; t < N; ++t)
-      if (t < n) my[t] = (WT)(uint32_t)rid[t];  // row ids are non-negative
+    for (int t = 0; t < NCOL; ++t)
+      if (t < nc) my[t] = NC == 0 ? (WT)(uint32_t)rid[t] : (WT)rid[t];  // row ids are non-negative
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -435,37 +490,57 @@ __global__ void __launch_bounds__(GJ_BLOCK) k_desum_unit(gjk::DesumArgs a, const
   }
 }
 
-template <int N, bool TS>
-void launch_unit(hipStream_t s, const gjk::DesumArgs& a, int rowid_bytes, int blocks, int64_t* range, int32_t* rec,
-                 int64_t cap) {
-  const size_t lds = (size_t)GJ_WAVES * unit_wave_lds(N, rowid_bytes, TS);
+template <int N, typename WT, bool TS, int NC>
+void launch_unit(hipStream_t s, const gjk::DesumArgs& a, int blocks, int64_t* range, int32_t* rec, int64_t cap) {
+  const size_t lds = (size_t)GJ_WAVES * unit_wave_lds(n_fields(N, TS, NC), (NC == 0 ? N : NC) * (int)sizeof(WT));
   if (rec) {
     hipLaunchKernelGGL(k_unit_range, dim3(1), dim3(64), 0, s, a, range);
     const int64_t rb = (cap + GJ_BLOCK - 1) / GJ_BLOCK;
-    hipLaunchKernelGGL((k_unit_records<N, TS>), dim3((unsigned)rb), dim3(GJ_BLOCK), 0, s, a, range, rec, cap);
-    if (rowid_bytes == 4)
-      hipLaunchKernelGGL((k_desum_unit<N, int32_t, true, TS>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec,
-                         cap);
-    else
-      hipLaunchKernelGGL((k_desum_unit<N, int64_t, true, TS>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec,
-                         cap);
+    hipLaunchKernelGGL((k_unit_records<N, TS, NC>), dim3((unsigned)rb), dim3(GJ_BLOCK), 0, s, a, range, rec, cap);
+    hipLaunchKernelGGL((k_desum_unit<N, WT, true, TS, NC>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec,
+                       cap);
   } else {
-    if (rowid_bytes == 4)
-      hipLaunchKernelGGL((k_desum_unit<N, int32_t, false, TS>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec,
-                         cap);
-    else
-      hipLaunchKernelGGL((k_desum_unit<N, int64_t, false, TS>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec,
-                         cap);
+    hipLaunchKernelGGL((k_desum_unit<N, WT, false, TS, NC>), dim3(blocks), dim3(GJ_BLOCK), lds, s, a, range, rec,
+                       cap);
   }
 }
 
+// row ids: exact table count up to 8, else the instance for any count
 template <int N>
-void launch_unit_ts(hipStream_t s, const gjk::DesumArgs& a, int rowid_bytes, int blocks, int64_t* range, int32_t* rec,
-                    int64_t cap, bool tl_single) {
+void launch_rows(hipStream_t s, const gjk::DesumArgs& a, int rowid_bytes, int blocks, int64_t* range, int32_t* rec,
+                 int64_t cap, bool tl_single) {
+  if (rowid_bytes == 4) {
+    if (tl_single)
+      launch_unit<N, int32_t, true, 0>(s, a, blocks, range, rec, cap);
+    else
+      launch_unit<N, int32_t, false, 0>(s, a, blocks, range, rec, cap);
+  } else {
+    if (tl_single)
+      launch_unit<N, int64_t, true, 0>(s, a, blocks, range, rec, cap);
+    else
+      launch_unit<N, int64_t, false, 0>(s, a, blocks, range, rec, cap);
+  }
+}
+
+// value columns: at most 4, 8 or 16 tables and 4, 8 or 16 columns
+template <int N, int NC>
+void launch_values_nc(hipStream_t s, const gjk::DesumArgs& a, int blocks, int64_t* range, int32_t* rec, int64_t cap,
+                      bool tl_single) {
   if (tl_single)
-    launch_unit<N, true>(s, a, rowid_bytes, blocks, range, rec, cap);
+    launch_unit<N, int32_t, true, NC>(s, a, blocks, range, rec, cap);
   else
-    launch_unit<N, false>(s, a, rowid_bytes, blocks, range, rec, cap);
+    launch_unit<N, int32_t, false, NC>(s, a, blocks, range, rec, cap);
+}
+
+template <int N>
+void launch_values_n(hipStream_t s, const gjk::DesumArgs& a, int blocks, int64_t* range, int32_t* rec, int64_t cap,
+                     bool tl_single) {
+  if (a.n_cols <= 4)
+    launch_values_nc<N, 4>(s, a, blocks, range, rec, cap, tl_single);
+  else if (a.n_cols <= 8)
+    launch_values_nc<N, 8>(s, a, blocks, range, rec, cap, tl_single);
+  else
+    launch_values_nc<N, GJ_MAX_OUT_COLS>(s, a, blocks, range, rec, cap, tl_single);
 }
 
 }  // namespace
@@ -478,22 +553,25 @@ int64_t desum_unit_blocks(int64_t n_rows) {
   return (blocks + 7) / 8 * 8;  // whole XCD rounds for the block remap
 }
 
-int64_t desum_unit_record_bytes(int64_t cap, int n_tables, bool tl_single) {
-  return cap * (int64_t)n_fields(n_tables, tl_single) * 4;
+int64_t desum_unit_record_bytes(int64_t cap, int n_tables, bool tl_single, int n_cols) {
+  return cap * (int64_t)n_fields(n_tables, tl_single, n_cols) * 4;
 }
 
-int64_t desum_unit_record_entries(int64_t n_root, int64_t n_rows, int n_tables, int rowid_bytes, bool tl_single) {
+int64_t desum_unit_record_entries(int64_t n_root, int64_t n_rows, int n_tables, bool tl_single, int n_cols,
+                                  int tuple_bytes) {
   // the chunk's ranks span at most min(n_root, n_rows) root entries; records
   // only when they take at most a quarter of the chunk's output bytes
   const int64_t cap = std::min(n_root, n_rows);
-  const int64_t rec_bytes = desum_unit_record_bytes(cap, n_tables, tl_single);
-  return rec_bytes * 4 <= n_rows * (int64_t)n_tables * rowid_bytes ? cap : 0;
+  const int64_t rec_bytes = desum_unit_record_bytes(cap, n_tables, tl_single, n_cols);
+  return rec_bytes * 4 <= n_rows * (int64_t)tuple_bytes ? cap : 0;
 }
 
 int desummarize_unit(hipStream_t s, const DesumArgs& a0, int rowid_bytes, int n_tables, bool tl_single, int64_t* range,
                      int32_t* rec, int64_t cap) {
   if (a0.n_rows <= 0) return 0;
-  if (n_tables < 2 || n_tables > GJ_MAX_TABLES || (rowid_bytes != 4 && rowid_bytes != 8) || a0.n_cols != 0 ||
+  const bool values = a0.n_cols > 0;
+  if (n_tables < 2 || n_tables > GJ_MAX_TABLES || (rowid_bytes != 4 && rowid_bytes != 8) ||
+      (values && (rowid_bytes != 4 || a0.n_cols > GJ_MAX_OUT_COLS)) ||
       (rec && (!range || cap < std::min(a0.n_root, a0.n_rows))))
     return -1;
   const int64_t blocks = desum_unit_blocks(a0.n_rows);
@@ -501,15 +579,24 @@ int desummarize_unit(hipStream_t s, const DesumArgs& a0, int rowid_bytes, int n_
   DesumArgs a = a0;
   a.n_tables = n_tables;
   const int nb = (int)blocks;
+  if (values) {
+    if (n_tables <= 4)
+      launch_values_n<4>(s, a, nb, range, rec, cap, tl_single);
+    else if (n_tables <= 8)
+      launch_values_n<8>(s, a, nb, range, rec, cap, tl_single);
+    else
+      launch_values_n<GJ_MAX_TABLES>(s, a, nb, range, rec, cap, tl_single);
+    return 0;
+  }
   switch (n_tables) {
-    case 2: launch_unit_ts<2>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
-    case 3: launch_unit_ts<3>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
-    case 4: launch_unit_ts<4>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
-    case 5: launch_unit_ts<5>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
-    case 6: launch_unit_ts<6>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
-    case 7: launch_unit_ts<7>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
-    case 8: launch_unit_ts<8>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
-    default: launch_unit_ts<GJ_MAX_TABLES>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 2: launch_rows<2>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 3: launch_rows<3>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 4: launch_rows<4>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 5: launch_rows<5>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 6: launch_rows<6>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 7: launch_rows<7>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    case 8: launch_rows<8>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
+    default: launch_rows<GJ_MAX_TABLES>(s, a, rowid_bytes, nb, range, rec, cap, tl_single); break;
   }
   return 0;
 }

@@ -56,8 +56,9 @@ struct DesumPlan {
 DesumPlan desum_plan(int n_tables, int rowid_bytes, int n_cols, int64_t n_rows, int rounds_per_lane, int stage);
 // returns -1 if the launch does not fit one grid
 int desummarize(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables, int rounds_per_lane, int stage);
-// Row-id expansion of a summary whose middle tables hold one entry per group
-// (desum_unit.hip); 0 on success, -1 for unsupported arguments.  tl_single:
+// Expansion of a summary whose middle tables hold one entry per group
+// (desum_unit.hip): row ids (a.n_cols = 0) or a.n_cols int32 value columns
+// (rowid_bytes 4); 0 on success, -1 for unsupported arguments.  tl_single:
 // the innermost table holds one entry per group too.  With `rec` (int32,
 // desum_unit_record_bytes of `cap` entries, cap from
 // desum_unit_record_entries) and `range` (2 int64) the root entries' records
@@ -65,8 +66,9 @@ int desummarize(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables
 int desummarize_unit(hipStream_t s, const DesumArgs& a, int rowid_bytes, int n_tables, bool tl_single, int64_t* range,
                      int32_t* rec, int64_t cap);
 int64_t desum_unit_blocks(int64_t n_rows);
-int64_t desum_unit_record_entries(int64_t n_root, int64_t n_rows, int n_tables, int rowid_bytes, bool tl_single);
-int64_t desum_unit_record_bytes(int64_t cap, int n_tables, bool tl_single);
+int64_t desum_unit_record_entries(int64_t n_root, int64_t n_rows, int n_tables, bool tl_single, int n_cols,
+                                  int tuple_bytes);
+int64_t desum_unit_record_bytes(int64_t cap, int n_tables, bool tl_single, int n_cols);
 // value columns (desum_values.hip): tuples per staging round, and the launch
 int value_round(int n_tables, int n_cols);
 void launch_values(hipStream_t s, const DesumArgs& a, int blocks);

@@ -225,3 +225,69 @@ def test_records_decoded_in_place_when_scratch_is_refused(oracle_mod):
     gc.collect()
     torch.cuda.synchronize()
     assert not state["live"]
+
+
+def _payload(q, seed):
+    """One seeded int32 payload column (full int32 range) per table."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 91])))
+    return [rng.integers(-2**31, 2**31 - 1, size=q.n_rows(t), dtype=np.int64).astype(np.int32)
+            for t in range(q.n_tables)]
+
+
+def _value_cases():
+    # (query, picks): picks are (table, "key"/"pay", column); the column counts
+    # reach the 4-, 8- and 16-column instances
+    star1 = _star(1, 20000, (400, 60, 150, 250), 3000, 400, 0.9)
+    star2 = _star(2, 15000, (300, 40, 90, 120), 2500, 300, 0.9, dup_fact=3000)
+    star3 = _star(3, 12000, (300, 40, 90, 120), 2000, 300, 0.7, dup_dim=40)
+    star4 = _star(4, 12000, (300, 40, 90, 120), 2500, 300, 0.9, bridge_extra=6)
+    chain = _chain_keyed_middle(7, 6000, 900, 4000, 300, 0.8)
+    one = _one_tuple_blocks(8, 70001)
+    star9 = _star(13, 8000, (100, 30, 40, 50, 60, 70, 80), 1500, 100, 0.8)
+    every = lambda q: [(t, "pay", 0) for t in range(q.n_tables)]  # noqa: E731
+    return [
+        (star1, every(star1) + [(1, "key", 1), (5, "key", 0)]),
+        (star2, [(0, "pay", 0), (0, "key", 2), (3, "pay", 0), (5, "pay", 0)]),
+        (star3, every(star3) + [(4, "key", 0)]),
+        (star4, every(star4) + [(5, "key", 1), (0, "key", 0)]),
+        (chain, [(1, "pay", 0), (2, "key", 1), (0, "key", 0)]),
+        (one, [(1, "key", 1), (0, "pay", 0), (1, "pay", 0)]),
+        (star9, every(star9) + [(0, "key", 3), (1, "key", 1)]),
+    ]
+
+
+@pytest.mark.parametrize("case", _value_cases(), ids=lambda c: f"{c[0].name}_{len(c[1])}cols")
+def test_keyed_lookup_values_match_oracle(gctx, oracle_mod, case):
+    """Value columns (payload gather) through the keyed-lookup expansion:
+    every value equals the host column at the oracle's row id, whole and in
+    ragged windows, and the general kernel gives the same values."""
+    import torch
+
+    from paper_2206_10435_amd import gj
+
+    q, picks = case
+    o = oracle_mod.Oracle(q)
+    ref_rows = o.canonical_result()
+    pay = _payload(q, 5)
+    host = [np.ascontiguousarray(q.tables[t][i] if src == "key" else pay[t], dtype=np.int32) for t, src, i in picks]
+    ref = np.stack([h[ref_rows[:, t]] for (t, _, _), h in zip(picks, host)], axis=1)
+    s = gctx.summarize(gctx.build_factors(gj.to_device_tables(q), q.parent, q.sep_col, q.parent_col))
+    Q = s.join_size
+    assert Q == len(ref) and gctx.desum_kernel(s) == "unit"
+    cs = gctx.colset(s, [(t, torch.from_numpy(h).to("cuda:0")) for (t, _, _), h in zip(picks, host)])
+    nc = len(picks)
+    _say("case unit values", q.name, "cols", nc, "Q", Q)
+
+    def values(first, count):
+        out = torch.full((max(count, 1) * nc,), -7, dtype=torch.int32, device="cuda:0")
+        nw = gctx.desummarize_values(s, cs, first, count, out)
+        assert nw == count
+        return out[: nw * nc].view(nw, nc).cpu().numpy()
+
+    for first, cnt in [(0, Q), (1, min(63, Q - 1)), (Q // 3 + 5, min(4104, Q - Q // 3 - 5)), (Q - 100, 100)]:
+        assert np.array_equal(values(first, cnt), ref[first:first + cnt]), (first, cnt)
+    try:
+        gctx.set_tune(desum_general=1)
+        assert np.array_equal(values(0, Q), ref)
+    finally:
+        gctx.set_tune()
