@@ -257,7 +257,10 @@ void gj_free_colset(gj_colset* cs);
  * row is column j of the set at that result row's row id of table tab[j].
  * `out` is a 16-byte aligned device buffer; rows past the join size are not
  * written and *n_written (host) receives the count; first_row > join size ->
- * GJ_E_RANGE; a set made for other factors -> GJ_E_INVALID. */
+ * GJ_E_RANGE; a set made for other factors -> GJ_E_INVALID.  Like
+ * gj_desummarize, it takes the keyed-lookup expansion where gj_desum_kernel
+ * says so, and may then take stream-ordered scratch for root-entry records
+ * (released before it returns; decoded in place if the allocation fails). */
 gj_status gj_desummarize_values(gj_ctx* ctx, const gj_summary* s, const gj_colset* cs, int64_t first_row,
                                 int64_t n_rows, int32_t* out, int64_t* n_written);
 
@@ -507,14 +510,15 @@ typedef struct {
 gj_status gj_desum_launch_config(int32_t n_tables, int32_t rowid_bytes, int32_t n_cols, int64_t n_rows,
                                  const gj_tune* tune, gj_desum_launch* out);
 
-/* Which kernel gj_desummarize takes for summary s on this context: 1 for the
- * keyed-lookup expansion, 0 for the general one (the result is the same).
- * The keyed-lookup expansion (Sec. 3.6's order, decoded per rank) applies to
- * row-id summaries of two or more tables in which every table other than the
- * root and the innermost table holds exactly one surviving entry per
- * surviving group (MC == GC in gj_summary_table), as a dimension joined on
- * its key does; the context's tune can switch it off (desum_general).  Reads
- * the summary's counts, which a batch summary fetches on first use. */
+/* Which kernel gj_desummarize and gj_desummarize_values take for summary s on
+ * this context: 1 for the keyed-lookup expansion, 0 for the general one (the
+ * result is the same).  The keyed-lookup expansion (Sec. 3.6's order, decoded
+ * per rank) applies to row-id summaries of two or more tables in which every
+ * table other than the root and the innermost table holds exactly one
+ * surviving entry per surviving group (MC == GC in gj_summary_table), as a
+ * dimension joined on its key does; the context's tune can switch it off
+ * (desum_general).  Reads the summary's counts, which a batch summary fetches
+ * on first use. */
 gj_status gj_desum_kernel(gj_ctx* ctx, const gj_summary* s, int32_t* kind);
 
 /* Plumbing for bindings and tests: copies `bytes` of device memory to host
