@@ -291,3 +291,31 @@ def test_keyed_lookup_values_match_oracle(gctx, oracle_mod, case):
         assert np.array_equal(values(0, Q), ref)
     finally:
         gctx.set_tune()
+
+
+def test_reloaded_summary_takes_the_keyed_lookup_expansion(gctx, oracle_mod, tmp_path):
+    """A star summary written to a file and loaded back carries the counts the
+    kernel choice reads: the reloaded summary takes the keyed-lookup expansion
+    and gives the oracle's tuples and values."""
+    import torch
+
+    from paper_2206_10435_amd import gj
+
+    q = _star(14, 12000, (300, 40, 90, 120), 2500, 300, 0.9, dup_fact=1500)
+    o = oracle_mod.Oracle(q)
+    ref = o.canonical_result().astype(np.int64)
+    s = gctx.summarize(gctx.build_factors(gj.to_device_tables(q), q.parent, q.sep_col, q.parent_col))
+    path = str(tmp_path / "star.gjs")
+    gctx.save(s, path, with_rows=True)
+    r = gctx.load(path)
+    Q = r.join_size
+    assert Q == len(ref) and gctx.desum_kernel(r) == "unit"
+    _say("case reloaded star", q.name, "Q =", Q)
+    for dt in (torch.int32, torch.int64):
+        assert np.array_equal(_desum(gctx, r, q.n_tables, 0, Q, dt), ref), dt
+    pay = _payload(q, 9)
+    cs = gctx.colset(r, [(t, torch.from_numpy(pay[t]).to("cuda:0")) for t in range(q.n_tables)])
+    out = torch.full((Q * q.n_tables,), -7, dtype=torch.int32, device="cuda:0")
+    assert gctx.desummarize_values(r, cs, 0, Q, out) == Q
+    exp = np.stack([pay[t][ref[:, t]] for t in range(q.n_tables)], axis=1)
+    assert np.array_equal(out.view(Q, q.n_tables).cpu().numpy(), exp)
