@@ -491,9 +491,11 @@ const int32_t* gj_batch_status(const gj_batch* b);
 gj_status gj_batch_summary(gj_batch* b, int32_t q, const gj_summary** out);
 void gj_free_batch(gj_batch* b);
 
-/* Launch shape that gj_desummarize (n_cols = 0, rowid_bytes 4 or 8) or
- * gj_desummarize_values (n_cols value columns, rowid_bytes 4) uses for n_rows
- * rows of an n_tables-table summary under `tune` (NULL: defaults).  Host
+/* Launch shape of the general expansion kernel that gj_desummarize (n_cols =
+ * 0, rowid_bytes 4 or 8) or gj_desummarize_values (n_cols value columns,
+ * rowid_bytes 4) uses for n_rows rows of an n_tables-table summary under
+ * `tune` (NULL: defaults) -- for summaries that gj_desum_kernel reports 0 for,
+ * or under desum_general = 1.  Host
  * only, no device work: lets tests and tuners check every setting's launch
  * against the kernel's limits.  GJ_E_INVALID for arguments or shapes the
  * kernel does not support (the expansion entry points then fail the same way). */
