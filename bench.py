@@ -257,16 +257,21 @@ def _batch_attempts():
     return att
 
 
-def payload_leg(ctx, torch, q, s, chunk_rows):
-    """Payload gather on the same summary: the two int32 payload columns of
-    every table (8 values, 32 bytes per tuple) materialized through the
-    expansion kernel, beside the row-id output of the same chunks."""
+def payload_leg(ctx, torch, q, s, chunk_rows, tabs):
+    """Payload gather on the same summary: the int32 payload columns of every
+    table (chain4: two per table, 8 values, 32 bytes per tuple), or for a
+    workload without payload columns (the star) each table's first key column,
+    materialized through the expansion kernel, beside the row-id output of the
+    same chunks."""
     from paper_2206_10435_amd import gj  # noqa: F401
 
     dev = "cuda:0"
     st = ctx.stream
-    pay = [[torch.from_numpy(c).to(dev) for c in p] for p in q.payload]
-    cols = [(t, pay[t][i]) for t in range(q.n_tables) for i in range(len(pay[t]))]
+    if q.payload:
+        pay = [[torch.from_numpy(c).to(dev) for c in p] for p in q.payload]
+        cols = [(t, pay[t][i]) for t in range(q.n_tables) for i in range(len(pay[t]))]
+    else:
+        cols = [(t, tabs[t][0]) for t in range(q.n_tables)]
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(st)
@@ -290,6 +295,8 @@ def payload_leg(ctx, torch, q, s, chunk_rows):
     avg = float(np.mean(ms))
     return {
         "columns": nc,
+        "source": "payload columns" if q.payload else "each table's first key column",
+        "kernel": ctx.desum_kernel(s),
         "bytes_per_tuple": nc * 4,
         "colset_ms": colset_ms,
         "expand_ms_per_chunk": avg,
@@ -586,9 +593,8 @@ def main():
         del out
         torch.cuda.empty_cache()
         s = ctx.summarize(ctx.build_factors(tabs, q.parent, q.sep_col, q.parent_col))
-        if q.payload:
-            rec["payload"] = payload_leg(ctx, torch, q, s, chunk_rows)
-            torch.cuda.empty_cache()
+        rec["payload"] = payload_leg(ctx, torch, q, s, chunk_rows, tabs)
+        torch.cuda.empty_cache()
         if args.workload == "chain4":
             rec["projection"] = projection_leg(ctx, torch, tabs, q, Q)
             torch.cuda.empty_cache()
