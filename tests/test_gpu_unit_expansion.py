@@ -319,3 +319,47 @@ def test_reloaded_summary_takes_the_keyed_lookup_expansion(gctx, oracle_mod, tmp
     assert gctx.desummarize_values(r, cs, 0, Q, out) == Q
     exp = np.stack([pay[t][ref[:, t]] for t in range(q.n_tables)], axis=1)
     assert np.array_equal(out.view(Q, q.n_tables).cpu().numpy(), exp)
+
+
+def test_block_offsets_beyond_32_bits(gctx, oracle_mod):
+    """One key shared by 1e5 rows on each side, the child's rows split over two
+    entries: the root entry's block holds 1e10 tuples and each child entry's
+    5e9, so offsets inside a block pass 2^32 (the 64-bit split, with the search
+    inside the innermost group).  Short windows (records decoded in place) are
+    compared tuple by tuple with the oracle's unrank; a 1e6-tuple window across
+    2^32 (records written first) is checked whole by the oracle's checker, with
+    the oracle's rank of its ends.  Both kernels."""
+    import torch
+
+    from paper_2206_10435_amd import gj
+
+    rng = np.random.default_rng(22)
+    n = 100_000
+    ra = np.concatenate([np.zeros(n, np.int64), rng.integers(1, 50, size=1000)])
+    sa = np.concatenate([np.zeros(n, np.int64), rng.integers(1, 50, size=1000)])
+    sx = np.concatenate([rng.integers(0, 2, size=n), rng.integers(0, 5, size=1000)])
+    p1, p2 = rng.permutation(len(ra)), rng.permutation(len(sa))
+    q = W.Query("pair_huge_block", [[ra[p1].astype(np.int32)], [sa[p2].astype(np.int32), sx[p2].astype(np.int32)]],
+                [-1, 0], [0, 0], [0, 0])
+    o = oracle_mod.Oracle(q)
+    Q, ovf = o.join_size()
+    assert not ovf and Q > 10**10
+    s = gctx.summarize(gctx.build_factors(gj.to_device_tables(q), q.parent, q.sep_col, q.parent_col))
+    assert s.join_size == Q and gctx.desum_kernel(s) == "unit"
+    _say("case huge block, Q =", Q)
+    short = [(2**32 - 3, 7), (5 * 10**9 + 2**32 + 11, 9), (Q - 10, 10)]
+    try:
+        for general in (0, 1):
+            gctx.set_tune(desum_general=general)
+            for first, cnt in short:
+                got = _desum(gctx, s, 2, first, cnt, torch.int64)
+                exp = np.stack([o.unrank(first + i) for i in range(cnt)]).astype(np.int64)
+                assert np.array_equal(got, exp), (general, first)
+            first, cnt = 2**32 - 500_000, 1_000_000
+            got = _desum(gctx, s, 2, first, cnt, torch.int64)
+            assert o.check_tuples(got) == -1, general
+            assert o.rank(got[0].astype(np.int32)) == first and o.rank(got[-1].astype(np.int32)) == first + cnt - 1
+            for i in (0, 499_999, 500_000, 500_001, cnt - 1):
+                assert np.array_equal(got[i], o.unrank(first + i)), (general, i)
+    finally:
+        gctx.set_tune()
