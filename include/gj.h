@@ -145,6 +145,13 @@ typedef struct {
   const int32_t* perm;
 } gj_factor_view;
 gj_status gj_factor_table(const gj_factors* f, int32_t t, gj_factor_view* v);
+/* How table t's rows were sorted for the group-by (host only, no device work):
+ * *kind = 0: one global radix pass per digit; 1: global passes over the top
+ * two digits, then each run of equal top bits sorted in LDS (gj_tune
+ * sort_local_rows); 2: as 1, but a run was longer than one block holds and
+ * the table was sorted again by the per-digit passes.  Same entries in every
+ * case. */
+gj_status gj_factor_sort(const gj_factors* f, int32_t t, int32_t* kind);
 void gj_free_factors(gj_factors* f);
 
 /* ---- stage 2: summary (Sec. 3.3 Algorithm 2 upward; Sec. 3.5 downward) ----
@@ -463,6 +470,13 @@ typedef struct {
   int32_t desum_general;   /* 0: gj_desummarize takes the keyed-lookup expansion for
                               the summaries it applies to (gj_desum_kernel); 1: always
                               the general expansion kernel (same result) */
+  int32_t sort_local_rows; /* gj_build_factors only: a table of at least this many rows
+                              whose sort words take 128 bits is sorted by two global
+                              passes over its top digits and an LDS sort of each run
+                              of equal top bits, instead of one global pass per digit
+                              (0: never; default 2^20).  Same result; a run longer
+                              than one block holds makes the build wait for the host
+                              once and sort that table in full. */
 } gj_tune;
 gj_status gj_batch_create(gj_ctx* ctx, int32_t n_queries, const int32_t* q_off, const gj_table* tables,
                           const gj_join_graph* graphs, const gj_tune* tune, gj_batch** out);

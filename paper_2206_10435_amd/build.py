@@ -28,8 +28,8 @@ FLAGS = [
     "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
-SOURCES = ["factor.hip", "summary.hip", "desum.hip", "desum_unit.hip", "desum_values.hip", "desum_runs.hip", "project.hip",
-           "weighted.hip", "gfjs.hip", "api.hip", "batch.hip", "batch_persist.hip", "store.hip",
+SOURCES = ["factor.hip", "sort_local.hip", "summary.hip", "desum.hip", "desum_unit.hip", "desum_values.hip",
+           "desum_runs.hip", "project.hip", "weighted.hip", "gfjs.hip", "api.hip", "batch.hip", "batch_persist.hip", "store.hip",
            "jtree.hip", "pjoin.hip", "cyclic.hip"]
 
 

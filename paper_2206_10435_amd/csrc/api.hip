@@ -291,6 +291,21 @@ static gj_status pack_layout(Plan& P, int t, const int32_t* mm) {
   d.sort_tile = GJ_BLOCK * P.sort_items[d.wide];
   d.ntiles_sort = (int32_t)((h.n + d.sort_tile - 1) / d.sort_tile);
   d.final_buf = d.npasses & 1;
+  d.sh0 = d.rb;
+  d.npasses_full = d.npasses;
+  d.local = 0;
+  // Large 128-bit-word tables: global passes over the top two digits only
+  // (buckets of about n / 2^(2 dbits) rows when the keys spread), then every
+  // bucket sorted in LDS (sort_local.hip) into words[1].  A block takes
+  // buckets of up to 1216 rows wherever they start: tables whose buckets
+  // would average over 1000 rows keep the per-digit passes.
+  if (P.local_rows > 0 && d.wide && h.n >= P.local_rows && d.npasses >= 3 &&
+      h.n <= ((int64_t)1000 << (2 * d.dbits))) {
+    d.local = 1;
+    d.sh0 = d.rb + d.keybits - 2 * d.dbits;
+    d.npasses = 2;
+    d.final_buf = 1;
+  }
   return GJ_OK;
 }
 
@@ -363,6 +378,7 @@ gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
   gj_ctx* ctx = P.ctx;
   hipStream_t s = ctx->stream;
   P.radix_bits = ctx->tune.radix_bits;
+  P.local_rows = P.allow_local ? ctx->tune.sort_local_rows : 0;
   P.sort_items[0] = ctx->tune.sort_items == 8 ? 8 : 16;
   P.sort_items[1] = 8;  // 128-bit words: 8 per thread (measured best of 4, 8, 16)
   fill_desc_static(P);
@@ -445,6 +461,16 @@ gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
       P.sort[w].push_back(P.add_list(tp, 0, true));
     }
   }
+  {
+    std::vector<int> lt;
+    for (int t = 0; t < P.nt; ++t)
+      if (P.td[t].local) lt.push_back(t);
+    P.local = P.add_list(lt, GJ_LOCAL_TILE, false);
+    P.local_full.clear();
+    for (int t : lt) P.local_full.push_back(P.add_list({t}, 0, true));
+    P.sort_kind.assign(P.nt, 0);
+    for (int t : lt) P.sort_kind[t] = 1;
+  }
   P.up.clear();
   for (int h = 0; h <= P.max_height; ++h) {
     std::vector<int> th;
@@ -505,11 +531,12 @@ gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
   F.agg = A.get_n<uint64_t>(P.agg_slots);
   F.agg2 = A.get_n<uint64_t>(P.agg_slots);
   F.didx = A.get_n<int32_t>(P.didx_slots);
+  F.lflag = A.get_n<int32_t>(P.nt);
   P.d_wl = A.get_n<WorkItem>(std::max<int64_t>((int64_t)P.wl_host.size(), 1));
   P.d_tabs = A.get_n<int32_t>(std::max<int64_t>((int64_t)P.tabs_host.size(), 1));
   P.d_desc = d_desc;
   if (!F.words[0] || !F.words[1] || !F.perm || !F.ekey || !F.estart || !F.eend || !F.egrp || !F.gval || !F.glo ||
-      !F.ghi || !F.cnt || !F.hist || !F.dtot || !F.agg || !F.agg2 || !F.didx || !P.d_wl || !P.d_tabs)
+      !F.ghi || !F.cnt || !F.hist || !F.dtot || !F.agg || !F.agg2 || !F.didx || !F.lflag || !P.d_wl || !P.d_tabs)
     return GJ_E_OOM;
   if ((st = check(hipMemcpyAsync(d_desc, P.td.data(), sizeof(TDesc) * P.nt, hipMemcpyHostToDevice, s), "upload")))
     return st;
@@ -527,13 +554,51 @@ gj_status plan_device(Plan& P, Arena& A, FPtrs& F) {
   return check(hipStreamSynchronize(s), "upload");
 }
 
-void launch_factors(const Plan& P, const FPtrs& F, hipStream_t s) {
+// Pack and sort the words of every table (the radix passes; for tables with
+// `local` set, the top-digit passes and the in-LDS bucket sort).
+static void launch_sort(const Plan& P, const FPtrs& F, hipStream_t s) {
   for (int w = 0; w < 2; ++w) gjk::pack(s, w, P.d_wl + P.allw[w].off, P.allw[w].n, P.d_desc, F);
   for (int p = 0; p < P.max_passes; ++p)
     for (int w = 0; w < 2; ++w) {
       const WL& l = P.sort[w][p];
       gjk::radix_pass(s, w, P.sort_items[w], P.d_wl + l.off, l.n, P.d_tabs + l.toff, l.tn, P.d_desc, F, p);
     }
+  if (P.local.n > 0) {
+    gjk::fill_i32(s, F.lflag, P.nt, 0, 0);
+    gjk::local_sort(s, P.d_wl + P.local.off, P.local.n, P.d_desc, F);
+  }
+}
+
+// Tables whose in-LDS bucket sort met a bucket longer than a block holds
+// (heavily repeated top bits): sorted again in full by the plain passes,
+// which take the bucket order (words[0]) as their input.  Waits for the host.
+static gj_status local_fallback(Plan& P, const FPtrs& F, hipStream_t s) {
+  std::vector<int32_t> fl(P.nt, 0);
+  gj_status st;
+  if ((st = check(hipMemcpyAsync(fl.data(), F.lflag, sizeof(int32_t) * P.nt, hipMemcpyDeviceToHost, s),
+                  "bucket sort")) ||
+      (st = check(hipStreamSynchronize(s), "bucket sort")))
+    return st;
+  int k = 0;
+  for (int t = 0; t < P.nt; ++t) {
+    TDesc& d = P.td[t];
+    if (!d.local) continue;
+    const WL& l = P.local_full[k++];
+    if (!fl[t]) continue;
+    d.local = 0;
+    P.sort_kind[t] = 2;
+    d.sh0 = d.rb;
+    d.npasses = d.npasses_full;
+    d.final_buf = d.npasses & 1;
+    if ((st = check(hipMemcpyAsync(P.d_desc + t, &d, sizeof(TDesc), hipMemcpyHostToDevice, s), "upload"))) return st;
+    for (int p = 0; p < d.npasses; ++p)
+      gjk::radix_pass(s, 1, P.sort_items[1], P.d_wl + l.off, l.n, P.d_tabs + l.toff, l.tn, P.d_desc, F, p);
+  }
+  return check(hipGetLastError(), "bucket sort");
+}
+
+// Entries and groups from the sorted words.
+static void launch_runs(const Plan& P, const FPtrs& F, hipStream_t s) {
   for (int w = 0; w < 2; ++w)
     gjk::runs(s, w, P.d_wl + P.allw[w].off, P.allw[w].n, nullptr, 0, P.d_desc, F);
   gjk::runs_scan(s, P.d_tabs + P.all.toff, P.all.tn, P.d_desc, F);
@@ -542,6 +607,11 @@ void launch_factors(const Plan& P, const FPtrs& F, hipStream_t s) {
     gjk::fill_i32(s, F.didx, P.didx_slots, -1, -1);
     gjk::group_index(s, P.d_wl + P.all.off, P.all.n, P.d_desc, F);
   }
+}
+
+void launch_factors(const Plan& P, const FPtrs& F, hipStream_t s) {
+  launch_sort(P, F, s);
+  launch_runs(P, F, s);
 }
 
 gj_status alloc_summary(const Plan& P, Arena& A, SPtrs& S) {
@@ -656,6 +726,7 @@ gj_status gj_ctx_create(int device, void* hip_stream, gj_alloc_fn alloc, gj_free
   c->tune.desum_stage = 4;
   c->tune.batch_task_rows = 0;
   c->tune.desum_general = 0;
+  c->tune.sort_local_rows = 1 << 20;
   *out = c;
   return GJ_OK;
 }
@@ -672,9 +743,11 @@ gj_status gj_ctx_set_tune(gj_ctx* ctx, const gj_tune* tune) {
   const int btr = tune->batch_task_rows;
   if ((tune->sort_items != 8 && tune->sort_items != 16) || tune->radix_bits < 4 || tune->radix_bits > 8 ||
       tune->desum_rounds < 0 || tune->desum_rounds > 1024 || !(stg == 2 || stg == 4 || stg == 8) ||
-      !(btr == 0 || (btr >= 256 && btr <= (1 << 24))) || (tune->desum_general != 0 && tune->desum_general != 1)) {
+      !(btr == 0 || (btr >= 256 && btr <= (1 << 24))) || (tune->desum_general != 0 && tune->desum_general != 1) ||
+      tune->sort_local_rows < 0) {
     set_error("gj_ctx_set_tune: sort_items in {8,16}, radix_bits in [4,8], desum_rounds in [0,1024], "
-              "desum_stage in {2,4,8}, batch_task_rows 0 or in [256, 2^24], desum_general 0 or 1");
+              "desum_stage in {2,4,8}, batch_task_rows 0 or in [256, 2^24], desum_general 0 or 1, "
+              "sort_local_rows >= 0");
     return GJ_E_INVALID;
   }
   ctx->tune = *tune;
@@ -693,17 +766,33 @@ gj_status gj_build_factors(gj_ctx* ctx, const gj_table* tables, const gj_join_gr
   if (st) return st;
   gj_factors* f = new gj_factors(ctx);
   f->plan.ctx = ctx;
+  f->plan.allow_local = true;
   int qoff[2] = {0, graph->n_tables};
   if ((st = plan_tables(f->plan, 1, qoff, tables, graph)) || (st = plan_device(f->plan, f->arena, f->F))) {
     delete f;
     return st;
   }
-  launch_factors(f->plan, f->F, ctx->stream);
+  launch_sort(f->plan, f->F, ctx->stream);
+  if (f->plan.local.n > 0 && (st = local_fallback(f->plan, f->F, ctx->stream))) {
+    delete f;
+    return st;
+  }
+  launch_runs(f->plan, f->F, ctx->stream);
   if ((st = check(hipGetLastError(), "factor kernels"))) {
     delete f;
     return st;
   }
   *out = f;
+  return GJ_OK;
+}
+
+gj_status gj_factor_sort(const gj_factors* f, int32_t t, int32_t* kind) {
+  GJ_SCOPE(f ? f->ctx : nullptr);
+  if (!f || !kind || t < 0 || t >= f->plan.nt || (int)f->plan.sort_kind.size() != f->plan.nt) {
+    set_error("gj_factor_sort: bad argument");
+    return GJ_E_INVALID;
+  }
+  *kind = f->plan.sort_kind[t];
   return GJ_OK;
 }
 

@@ -57,6 +57,9 @@ struct TDesc {
   int32_t keybits;          // total key bits
   int32_t wide;             // 1: 128-bit words, 0: 64-bit words
   int32_t npasses, dbits;   // radix passes over the key bits and digit width
+  int32_t sh0;              // bit position of digit 0 of the passes (rb, or the top digits' base)
+  int32_t local;            // 1: the passes take the top two digits, buckets are sorted in LDS
+  int32_t npasses_full;     // passes of the plain radix sort (host only)
   int32_t sort_tile;        // keys per sort tile
   int32_t final_buf;        // word buffer (0/1) holding the sorted words
   int32_t sepshift;         // (t >= 1) separator field position within the key bits
@@ -86,6 +89,9 @@ struct TDesc {
 #define DOWN_BUCKETS 256
 #define DOWN_PARENT_RATIO 4
 
+// Positions per block of the in-LDS bucket sort of large 128-bit-word tables.
+#define GJ_LOCAL_TILE 1024
+
 // Rows / entries per tile of the flat kernels (rounds of GJ_BLOCK elements).
 #define GJ_ROUNDS 16
 #define GJ_TILE (GJ_BLOCK * GJ_ROUNDS)
@@ -109,6 +115,7 @@ struct FPtrs {
   uint64_t* agg2;
   int64_t* ecnt;  // projected factors: entry frequencies (null: the row counts)
   int32_t* didx;  // dense separator value -> group indexes (see TDesc)
+  int32_t* lflag;  // per table: a bucket did not fit the in-LDS sort
 };
 
 // Pointers of a plan's summary arrays.

@@ -15,6 +15,9 @@ void pack(hipStream_t s, int wide, const WorkItem* wl, int nwl, const TDesc* D, 
 void rank_rows(hipStream_t s, const int32_t* perm, const int32_t* estart, int64_t m, int64_t n, int32_t* rank);
 void radix_pass(hipStream_t s, int wide, int items, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab,
                 const TDesc* D, const FPtrs& P, int pass);
+// sort_local.hip: the buckets of tables with `local` set, sorted in LDS
+// (words[0] -> words[1]); lflag[t] = 1 where a bucket is too long
+void local_sort(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F);
 void runs(hipStream_t s, int wide, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab, const TDesc* D,
           const FPtrs& P);
 void runs_scan(hipStream_t s, const int32_t* tabs, int ntab, const TDesc* D, const FPtrs& P);

@@ -93,6 +93,13 @@ struct Plan {
   TDesc* d_desc = nullptr;
   int sort_items[2] = {16, 8};
   int radix_bits = 8;
+  // bucket passes + in-LDS sort for 128-bit-word tables of at least
+  // local_rows rows (0: never; set only where the build may wait for the host)
+  bool allow_local = false;
+  int64_t local_rows = 0;
+  WL local;                  // GJ_LOCAL_TILE tiles of those tables
+  std::vector<WL> local_full;  // per such table: its sort tiles, for the full sort
+  std::vector<int8_t> sort_kind;  // per table: 0 per-digit passes, 1 bucket sort, 2 bucket sort redone in full
 
   WL add_list(const std::vector<int>& tables, int tile, bool sort_tiles);
 };

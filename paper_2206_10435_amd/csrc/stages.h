@@ -135,7 +135,7 @@ __device__ __forceinline__ void upsweep_body(const WorkItem w, const TDesc* __re
   const int db = d.dbits;
   const int nd = 1 << db;
   const uint32_t mask = (uint32_t)nd - 1;
-  const int shift = d.rb + pass * db;
+  const int shift = d.sh0 + pass * db;
   const auto* in = word_ptr<WIDE>((pass & 1) ? words1 : words0, d);
   for (int i = threadIdx.x; i < GJ_WAVES * 256; i += GJ_BLOCK) (&wh[0][0])[i] = 0;
   __syncthreads();
@@ -196,7 +196,7 @@ __device__ __forceinline__ void downsweep_body(const WorkItem w, const TDesc* __
   const int db = d.dbits;
   const int nd = 1 << db;
   const uint32_t mask = (uint32_t)nd - 1;
-  const int shift = d.rb + pass * db;
+  const int shift = d.sh0 + pass * db;
   const Word* in = word_ptr<WIDE>((pass & 1) ? words1 : words0, d);
   Word* out = word_ptr<WIDE>((pass & 1) ? words0 : words1, d);
   const int tid = threadIdx.x;

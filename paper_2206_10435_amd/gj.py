@@ -71,7 +71,8 @@ class _PotView(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("sort_items", C.c_int32), ("radix_bits", C.c_int32), ("desum_rounds", C.c_int32),
-                ("desum_stage", C.c_int32), ("batch_task_rows", C.c_int32), ("desum_general", C.c_int32)]
+                ("desum_stage", C.c_int32), ("batch_task_rows", C.c_int32), ("desum_general", C.c_int32),
+                ("sort_local_rows", C.c_int32)]
 
 
 class SummaryFileInfo(C.Structure):
@@ -100,6 +101,7 @@ SIGNATURES = {
     "gj_validate": (C.c_int, [_vp, _vp]),
     "gj_build_factors": (C.c_int, [_vp, _vp, _vp, _vp]),
     "gj_factor_table": (C.c_int, [_vp, _i32, _vp]),
+    "gj_factor_sort": (C.c_int, [_vp, _i32, _vp]),
     "gj_free_factors": (None, [_vp]),
     "gj_summarize": (C.c_int, [_vp, _vp, _vp, _vp]),
     "gj_summarize_batch": (C.c_int, [_vp, _vp, _i32, _vp, _vp, _vp]),
@@ -300,8 +302,9 @@ class Context:
             self.h = None
 
     def set_tune(self, sort_items=8, radix_bits=8, desum_rounds=0, desum_stage=4, batch_task_rows=0,
-                 desum_general=0):
-        t = Tune(sort_items, radix_bits, desum_rounds, desum_stage, batch_task_rows, desum_general)
+                 desum_general=0, sort_local_rows=1 << 20):
+        t = Tune(sort_items, radix_bits, desum_rounds, desum_stage, batch_task_rows, desum_general,
+                 sort_local_rows)
         self._check(self.L.gj_ctx_set_tune(self.h, C.byref(t)))
 
     def desum_kernel(self, s: "Summary") -> str:
@@ -569,6 +572,14 @@ class Factors:
         keys = np.stack([d(v.keys[c], M, np.int32) for c in range(k)], axis=1) if k else np.zeros((M, 0), np.int32)
         return dict(keys=keys, start=d(v.start, M, np.int32), end=d(v.end, M, np.int32),
                     count=d(v.count, M, np.int64), perm=d(v.perm, N, np.int32))
+
+    def sort_kind(self, t: int) -> str:
+        """How table t was sorted: 'digits' (a global pass per digit), 'buckets'
+        (top-digit passes, then an LDS sort of each bucket) or 'buckets_redone'
+        (a bucket too long for one block: sorted again by the per-digit passes)."""
+        k = C.c_int32(-1)
+        self.ctx._check(self.ctx.L.gj_factor_sort(self.h, t, C.byref(k)))
+        return ("digits", "buckets", "buckets_redone")[k.value]
 
 
 class Summary:

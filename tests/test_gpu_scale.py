@@ -171,6 +171,9 @@ def test_star_full_size(gctx):
     _say("star join size (closed form)", Q)
     tabs = gj.to_device_tables(q)
     f = gctx.build_factors(tabs, q.parent, q.sep_col, q.parent_col)
+    # the fact table's 75 key bits take the bucket sort (top two digits
+    # globally, each run of equal top bits in LDS), the dimensions one pass a digit
+    assert [f.sort_kind(t) for t in range(q.n_tables)] == ["buckets"] + ["digits"] * 5
     _factor_properties(f, q)
     _say("factors ok")
     s = gctx.summarize(f)
