@@ -141,15 +141,13 @@ __device__ __forceinline__ void upsweep_body(const WorkItem w, const TDesc* __re
   __syncthreads();
   const int64_t base = (int64_t)w.tile * (GJ_BLOCK * ITEMS);
   const int64_t cnt = min((int64_t)GJ_BLOCK * ITEMS, d.n - base);
-  const int wv = wave_id(), ln = lane_id();
+  const int wv = wave_id();
+  // counts only: any order, so block-strided loads and LDS adds into the
+  // wave's own histogram
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
-    int64_t li = (int64_t)wv * 64 * ITEMS + r * 64 + ln;
-    bool valid = li < cnt;
-    uint32_t dig = valid ? digit_of(in[base + li], shift, mask) : 0u;
-    uint64_t peers = match_digit(dig, valid, db);
-    bool leader = valid && (peers & lanemask_lt()) == 0;
-    if (leader) wh[wv][dig] += (uint32_t)__popcll(peers);
+    const int64_t li = (int64_t)r * GJ_BLOCK + threadIdx.x;
+    if (li < cnt) atomicAdd(&wh[wv][digit_of(in[base + li], shift, mask)], 1u);
   }
   __syncthreads();
   for (int g = threadIdx.x; g < nd; g += GJ_BLOCK) {
