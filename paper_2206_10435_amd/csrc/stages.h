@@ -653,6 +653,9 @@ constexpr int DOWN_ACC = (DOWN_MAX_GROUPS / DOWN_BUCKETS);  // groups of one buc
 constexpr int DT_STAGE = 2 * DOWN_BUCKETS * 4 + LDS_SCAN32 + 16;
 constexpr int LDS_DTILE = DT_STAGE + GJ_TILE * 12;
 constexpr int DOWN_RTILES = 8 * GJ_BLOCK;  // tiles of one reduce range at most
+#ifndef DOWN_RUNS
+#define DOWN_RUNS 4  // runs per 16-lane group in flight in the bucket sums
+#endif
 constexpr int LDS_DRED = DOWN_ACC * 8 + (2 * DOWN_RTILES + 1) * 4 + LDS_SCAN32 + 12;
 
 // Parent tile: each bucketed child's items in bucket order at the tile's
@@ -783,29 +786,41 @@ __device__ __forceinline__ void down_reduce_body(const WorkItem w, const TDesc* 
   if (threadIdx.x == 0) rbeg[nt] = carry;
   __syncthreads();
   const int64_t o = dc.link_off + (int64_t)t0 * GJ_TILE;
-  constexpr int U4 = 4;
-  for (uint32_t k0 = 0; k0 < carry; k0 += GJ_BLOCK * U4) {
-    int32_t key[U4];
-    uint64_t val[U4];
+  // each run (a tile's items of this bucket, contiguous) by a group of 16
+  // lanes, DOWN_RUNS runs per group at a time, every lane's loads before its adds
+  constexpr int RG = 16, NRG = GJ_BLOCK / RG;
+  const int q = threadIdx.x / RG, ql = threadIdx.x % RG;
+  for (int i0 = q; i0 < nt; i0 += DOWN_RUNS * NRG) {
+    uint32_t len[DOWN_RUNS];
+    int64_t at0[DOWN_RUNS];
+    uint32_t lm = 0;
 #pragma unroll
-    for (int u = 0; u < U4; ++u) {
-      const uint32_t k = k0 + u * GJ_BLOCK + threadIdx.x;
-      key[u] = -1;
-      if (k < carry) {
-        // run holding flat item k: the last run starting at or before k
-        int lo = 0, hi = nt;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (rbeg[mid] <= k) lo = mid; else hi = mid;
-        }
-        const int64_t at = o + (int64_t)lo * GJ_TILE + rsrc[lo] + (k - rbeg[lo]);
-        key[u] = S.dkey[at];
-        val[u] = (uint64_t)S.dval[at];
+    for (int r = 0; r < DOWN_RUNS; ++r) {
+      const int i = i0 + r * NRG;
+      len[r] = 0;
+      at0[r] = 0;
+      if (i < nt) {
+        len[r] = rbeg[i + 1] - rbeg[i];
+        at0[r] = o + (int64_t)i * GJ_TILE + rsrc[i];
       }
+      lm = max(lm, len[r]);
     }
+    for (uint32_t k = ql; k < lm; k += 2 * RG) {
+      int32_t key[2 * DOWN_RUNS];
+      uint64_t val[2 * DOWN_RUNS];
 #pragma unroll
-    for (int u = 0; u < U4; ++u)
-      if (key[u] >= 0) atomicAdd(&acc[key[u] - g0], (unsigned long long)val[u]);
+      for (int u = 0; u < 2 * DOWN_RUNS; ++u) {
+        const uint32_t kk = k + (u & 1) * RG;
+        key[u] = -1;
+        if (kk < len[u >> 1]) {
+          key[u] = S.dkey[at0[u >> 1] + kk];
+          val[u] = (uint64_t)S.dval[at0[u >> 1] + kk];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2 * DOWN_RUNS; ++u)
+        if (key[u] >= 0) atomicAdd(&acc[key[u] - g0], (unsigned long long)val[u]);
+    }
   }
   __syncthreads();
   unsigned long long* Dg = reinterpret_cast<unsigned long long*>(S.Dg + dc.off + g0);
