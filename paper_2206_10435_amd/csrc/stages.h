@@ -698,32 +698,38 @@ __device__ __forceinline__ void down_tile_body(const WorkItem w, const TDesc* __
     const int32_t* link = S.link + dc.link_off;
     const int shb = down_shift(F.cnt[ch * CNT_STRIDE + CNT_G]);
     cnt[tid] = 0;
+    // every load of this child first (a wave's loads return only after its
+    // earlier stores): links and products into registers, the stores last
+    int32_t jv[GJ_ROUNDS];
+    uint64_t xv[GJ_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < GJ_ROUNDS; ++r) {
+      const int64_t e = base + r * GJ_BLOCK + tid;
+      jv[r] = -1;
+      xv[r] = 0;
+      if (e < M) {
+        jv[r] = link[e];
+        xv[r] = (uint64_t)S.xprod[dc.link_off + e];
+      }
+    }
     __syncthreads();
     int32_t rk[GJ_ROUNDS];  // rank inside the bucket (-1: no item)
 #pragma unroll
     for (int r = 0; r < GJ_ROUNDS; ++r) {
-      const int64_t e = base + r * GJ_BLOCK + tid;
       rk[r] = -1;
-      if (e < M) {
-        const int32_t j = link[e];
-        if (j >= 0) rk[r] = (int32_t)atomicAdd(&cnt[j >> shb], 1u);
-      }
+      if (jv[r] >= 0) rk[r] = (int32_t)atomicAdd(&cnt[jv[r] >> shb], 1u);
     }
     __syncthreads();
     uint32_t tot;
     const uint32_t st = block_excl_sum(cnt[tid], sh, tot);
     start[tid] = st;
-    S.dhist[dc.dhist_off + (int64_t)tid * d.ntiles + w.tile] = st;
-    if (tid == 0) S.dhist[dc.dhist_off + (int64_t)DOWN_BUCKETS * d.ntiles + w.tile] = tot;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < GJ_ROUNDS; ++r) {
       if (rk[r] < 0) continue;
-      const int64_t e = base + r * GJ_BLOCK + tid;
-      const int32_t j = link[e];
-      const uint32_t p = start[j >> shb] + (uint32_t)rk[r];
-      skey[p] = j;
-      sval[p] = cd[r] ? smul(cd[r], (uint64_t)S.xprod[dc.link_off + e]) : 0ULL;
+      const uint32_t p = start[jv[r] >> shb] + (uint32_t)rk[r];
+      skey[p] = jv[r];
+      sval[p] = cd[r] ? smul(cd[r], xv[r]) : 0ULL;
     }
     __syncthreads();
     int32_t* okey = S.dkey + dc.link_off + base;
@@ -732,6 +738,8 @@ __device__ __forceinline__ void down_tile_body(const WorkItem w, const TDesc* __
       okey[i] = skey[i];
       oval[i] = (int64_t)sval[i];
     }
+    S.dhist[dc.dhist_off + (int64_t)tid * d.ntiles + w.tile] = st;
+    if (tid == 0) S.dhist[dc.dhist_off + (int64_t)DOWN_BUCKETS * d.ntiles + w.tile] = tot;
     __syncthreads();
   }
 }
@@ -947,18 +955,31 @@ __device__ __forceinline__ void compact_links_body(const WorkItem w, const TDesc
   if (d.nchild == 0) return;
   const int64_t M = F.cnt[w.t * CNT_STRIDE + CNT_M];
   const int64_t base = (int64_t)w.tile * GJ_TILE;
+  int32_t ci[GJ_ROUNDS];  // compacted index of each surviving entry, else -1
+#pragma unroll
   for (int r = 0; r < GJ_ROUNDS; ++r) {
     const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
-    if (e >= M) break;
-    const int64_t se = d.off + e;
-    if (!entry_survives(d, F, S, se)) continue;
-    const int32_t ci = S.e2c[se];
-    for (int i = 0; i < d.nchild; ++i) {
-      const TDesc& dc = D[d.child[i]];
+    ci[r] = -1;
+    if (e < M && entry_survives(d, F, S, d.off + e)) ci[r] = S.e2c[d.off + e];
+  }
+  // one child at a time, every round's gathers before its stores (a wave's
+  // loads return only after its earlier stores)
+  for (int i = 0; i < d.nchild; ++i) {
+    const TDesc& dc = D[d.child[i]];
+    const int4* grec = reinterpret_cast<const int4*>(S.grec + dc.off);
+    int4* crec = reinterpret_cast<int4*>(S.crec + dc.link_off);
+    const int32_t* link = S.link + dc.link_off + base + threadIdx.x;
+    int4 rec[GJ_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < GJ_ROUNDS; ++r) {
       // a surviving entry's child group survives (its message and its
       // downward message are both > 0)
-      S.crec[dc.link_off + ci] = S.grec[dc.off + S.link[dc.link_off + e]];
+      rec[r] = make_int4(0, 0, 0, 0);
+      if (ci[r] >= 0) rec[r] = grec[link[r * GJ_BLOCK]];
     }
+#pragma unroll
+    for (int r = 0; r < GJ_ROUNDS; ++r)
+      if (ci[r] >= 0) crec[ci[r]] = rec[r];
   }
 }
 
