@@ -90,7 +90,7 @@ struct TDesc {
 #define DOWN_PARENT_RATIO 4
 
 // Positions per block of the in-LDS bucket sort of large 128-bit-word tables.
-#define GJ_LOCAL_TILE 1024
+#define GJ_LOCAL_TILE 704
 
 // Rows / entries per tile of the flat kernels (rounds of GJ_BLOCK elements).
 #define GJ_ROUNDS 16

@@ -30,21 +30,26 @@
 
 namespace {
 
-// 512 threads and two 2240-word buffers: two blocks share a CU's LDS (one
-// block of 1024 threads sorting up to 4096 words ran 1.6 times longer).  With
-// tiles of 1024 positions a bucket of up to 1216 words fits wherever it starts.
+// 512 threads and one 1920-word buffer (40 KB of LDS with the histograms):
+// four blocks share a CU (two 4096-word buffers and 1024 threads, one block a
+// CU, ran 2.5 times longer).  With tiles of 704 positions a bucket of up to
+// 1216 words fits wherever it starts.
 constexpr int LS_BLOCK = 512;
-constexpr int LS_CAP = 2240;  // longest range a block sorts
+constexpr int LS_CAP = 1920;  // longest range a block sorts
 constexpr int LS_WAVES = LS_BLOCK / 64;
 constexpr int LS_ITEMS = (LS_CAP + LS_BLOCK - 1) / LS_BLOCK;  // most words per lane and LDS pass
 constexpr int LS_CHUNK = 512;                                 // words per look-ahead step
 constexpr int LS_SMALL = 96;  // longest sub-bucket ranked by counting
 static_assert(GJ_LOCAL_TILE < LS_CAP, "look-ahead room");
 static_assert(LS_CHUNK <= LS_BLOCK, "one look-ahead word per thread");
+static_assert(LS_CAP * 2 <= LS_WAVES * 256 * 4, "the indexes fit the histograms' room");
 
 struct LsShared {
-  W128 buf[2][LS_CAP];
-  uint32_t wh[LS_WAVES][256];  // per wave: digit counts, then their prefix over waves
+  W128 buf[LS_CAP];  // the range (a pass permutes it in place through registers)
+  union {
+    uint32_t wh[LS_WAVES][256];  // in a pass: per wave, digit counts, then their prefix over waves
+    uint16_t idx[LS_CAP];        // after the counting: the word that goes to each place
+  };
   uint32_t dstart[257];        // digit starts in the pass's output, then m
   uint32_t wmax[4];
   uint64_t orr[LS_WAVES][2];
@@ -58,11 +63,12 @@ __device__ __forceinline__ void note_head(bool head, int j, int32_t* pos) {
   if (b != 0 && lane_id() == __ffsll((long long)b) - 1) atomicMin(pos, j);
 }
 
-// One stable LDS pass: the m words of src ordered by their 8-bit digit at
-// `shift` into dst, ranked by wave ballots in input order (wave v takes words
-// [v 64 R, (v+1) 64 R), R rounds of 64).  Leaves digit g's words at
+// One stable LDS pass: the m words at S.buf[src ..] ordered by their 8-bit
+// digit at `shift` into S.buf[0 ..], ranked by wave ballots in input order
+// (wave v takes words [v 64 R, (v+1) 64 R), R rounds of 64).  Every word is
+// in a register before the first store.  Leaves digit g's words at
 // [S.dstart[g], S.dstart[g + 1]); returns the largest digit count.
-__device__ __forceinline__ int lds_pass(LsShared& S, const W128* src, W128* dst, int m, int R, int shift) {
+__device__ __forceinline__ int lds_pass(LsShared& S, int src, int m, int R, int shift) {
   const int tid = threadIdx.x, wv = wave_id(), ln = lane_id();
   for (int i = tid; i < LS_WAVES * 256; i += LS_BLOCK) (&S.wh[0][0])[i] = 0;
   __syncthreads();
@@ -73,7 +79,7 @@ __device__ __forceinline__ int lds_pass(LsShared& S, const W128* src, W128* dst,
     if (r >= R) break;
     const int j = wv * 64 * R + r * 64 + ln;
     const bool valid = j < m;
-    if (valid) key[r] = src[j];
+    if (valid) key[r] = S.buf[src + j];
     dig[r] = valid ? (uint32_t)shr128_lo(key[r].lo, key[r].hi, shift) & 255u : 0u;
     const uint64_t peers = match_digit(dig[r], valid, 8);
     const uint64_t below = peers & lanemask_lt();
@@ -111,7 +117,7 @@ __device__ __forceinline__ int lds_pass(LsShared& S, const W128* src, W128* dst,
   for (int r = 0; r < LS_ITEMS; ++r) {
     if (r >= R) break;
     const int j = wv * 64 * R + r * 64 + ln;
-    if (j < m) dst[S.dstart[dig[r]] + S.wh[wv][dig[r]] + rank[r]] = key[r];
+    if (j < m) S.buf[S.dstart[dig[r]] + S.wh[wv][dig[r]] + rank[r]] = key[r];
   }
   __syncthreads();
   return (int)max(max(S.wmax[0], S.wmax[1]), max(S.wmax[2], S.wmax[3]));
@@ -131,7 +137,7 @@ __global__ void __launch_bounds__(LS_BLOCK) k_local_sort(const WorkItem* __restr
   W128* out = word_ptr<1>(words1, d);
   const int sh0 = d.sh0;
 
-  for (int j = tid; j < tn; j += LS_BLOCK) S.buf[0][j] = in[t0 + j];
+  for (int j = tid; j < tn; j += LS_BLOCK) S.buf[j] = in[t0 + j];
   if (tid < 2) S.pos[tid] = INT_MAX;
   __syncthreads();
   // first bucket head in the tile
@@ -141,9 +147,9 @@ __global__ void __launch_bounds__(LS_BLOCK) k_local_sort(const WorkItem* __restr
     bool head = false;
     if (j < tn) {
       if (j == 0)
-        head = t0 == 0 || high_bits(wxor(in[t0 - 1], S.buf[0][0]), sh0);
+        head = t0 == 0 || high_bits(wxor(in[t0 - 1], S.buf[0]), sh0);
       else
-        head = high_bits(wxor(S.buf[0][j - 1], S.buf[0][j]), sh0);
+        head = high_bits(wxor(S.buf[j - 1], S.buf[j]), sh0);
     }
     note_head(head, j, &S.pos[0]);
   }
@@ -161,9 +167,9 @@ __global__ void __launch_bounds__(LS_BLOCK) k_local_sort(const WorkItem* __restr
       }
       const int cend = (int)min((int64_t)min(c0 + LS_CHUNK, LS_CAP), avail);
       const int j = c0 + tid;
-      if (j < cend) S.buf[0][j] = in[t0 + j];
+      if (j < cend) S.buf[j] = in[t0 + j];
       __syncthreads();
-      if (tid < LS_CHUNK) note_head(j < cend && high_bits(wxor(S.buf[0][j - 1], S.buf[0][j]), sh0), j, &S.pos[1]);
+      if (tid < LS_CHUNK) note_head(j < cend && high_bits(wxor(S.buf[j - 1], S.buf[j]), sh0), j, &S.pos[1]);
       __syncthreads();
       const int h = S.pos[1];
       if (h != INT_MAX) {
@@ -185,9 +191,9 @@ __global__ void __launch_bounds__(LS_BLOCK) k_local_sort(const WorkItem* __restr
   // key bits that vary inside the range (row-id bits excluded)
   uint64_t olo = 0, ohi = 0;
   {
-    const W128 f = S.buf[0][s_off];
+    const W128 f = S.buf[s_off];
     for (int j = s_off + tid; j < e_off; j += LS_BLOCK) {
-      const W128 x = S.buf[0][j];
+      const W128 x = S.buf[j];
       olo |= x.lo ^ f.lo;
       ohi |= x.hi ^ f.hi;
     }
@@ -219,42 +225,42 @@ __global__ void __launch_bounds__(LS_BLOCK) k_local_sort(const WorkItem* __restr
   const int npass = hb < d.rb ? 0 : (hb - d.rb) / 8 + 1;
 
   const int R = (m + LS_BLOCK - 1) / LS_BLOCK;  // words per lane and pass, over every wave
-  const W128* cur = &S.buf[0][s_off];
-  if (npass > 0) {
-    // the top varying digit first: sub-buckets of about m / 256 words
-    const int top = max(d.rb, hb - 7);
-    const int big = lds_pass(S, cur, S.buf[1], m, R, top);
-    cur = S.buf[1];
-    if (top > d.rb && big <= LS_SMALL) {
-      // each word's place inside its sub-bucket: the number of smaller words
-      // there (whole words compare as (key, row id), the order wanted)
-      for (int j = tid; j < m; j += LS_BLOCK) {
-        const W128 x = S.buf[1][j];
-        const uint32_t g = (uint32_t)shr128_lo(x.lo, x.hi, top) & 255u;
-        const int a = S.dstart[g], e = S.dstart[g + 1];
-        int rank = a;
-        for (int k = a; k < e; ++k) {
-          const W128 y = S.buf[1][k];
-          rank += (y.hi < x.hi || (y.hi == x.hi && y.lo < x.lo)) ? 1 : 0;
-        }
-        S.buf[0][rank] = x;
+  W128* o = out + t0 + s_off;
+  if (npass == 0) {
+    for (int j = tid; j < m; j += LS_BLOCK) o[j] = S.buf[s_off + j];
+    return;
+  }
+  // the top varying digit first: sub-buckets of about m / 256 words
+  const int top = max(d.rb, hb - 7);
+  const int big = lds_pass(S, s_off, m, R, top);
+  if (top > d.rb && big <= LS_SMALL) {
+    // each word's place inside its sub-bucket: the number of smaller words
+    // there (whole words compare as (key, row id), the order wanted)
+    for (int j = tid; j < m; j += LS_BLOCK) {
+      const W128 x = S.buf[j];
+      const uint32_t g = (uint32_t)shr128_lo(x.lo, x.hi, top) & 255u;
+      const int a = S.dstart[g], e = S.dstart[g + 1];
+      int rank = a;
+      for (int k = a; k < e; ++k) {
+        const W128 y = S.buf[k];
+        rank += (y.hi < x.hi || (y.hi == x.hi && y.lo < x.lo)) ? 1 : 0;
       }
-      __syncthreads();
-      cur = S.buf[0];
-    } else if (top > d.rb) {
-      // a long sub-bucket: LSD passes over every varying digit (stable, so
-      // equal keys keep their row order)
-      int b = 1;
-      for (int p = 0; p < npass; ++p) {
-        const int shift = d.rb + 8 * p;
-        if (((uint32_t)shr128_lo(olo, ohi, shift) & 255u) == 0) continue;  // digit constant in the range
-        lds_pass(S, S.buf[b], S.buf[b ^ 1], m, R, shift);
-        b ^= 1;
-      }
-      cur = S.buf[b];
+      S.idx[rank] = (uint16_t)j;
+    }
+    __syncthreads();
+    for (int j = tid; j < m; j += LS_BLOCK) o[j] = S.buf[S.idx[j]];
+    return;
+  }
+  if (top > d.rb) {
+    // a long sub-bucket: LSD passes over every varying digit (stable, so
+    // equal keys keep their row order)
+    for (int p = 0; p < npass; ++p) {
+      const int shift = d.rb + 8 * p;
+      if (((uint32_t)shr128_lo(olo, ohi, shift) & 255u) == 0) continue;  // digit constant in the range
+      lds_pass(S, 0, m, R, shift);
     }
   }
-  for (int j = tid; j < m; j += LS_BLOCK) out[t0 + s_off + j] = cur[j];
+  for (int j = tid; j < m; j += LS_BLOCK) o[j] = S.buf[j];
 }
 
 }  // namespace

@@ -13,8 +13,8 @@ from paper_2206_10435_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TILE = 1024  # positions per block of the LDS sort
-CAP = 2240  # longest range a block sorts
+TILE = 704  # positions per block of the LDS sort
+CAP = 1920  # longest range a block sorts
 
 
 def _say(*a):
