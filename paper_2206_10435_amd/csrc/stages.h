@@ -870,6 +870,11 @@ __device__ __forceinline__ void compact_count_body(const WorkItem w, const TDesc
   if (threadIdx.x == 0) F.agg[d.agg_off + w.tile] = tot;
 }
 
+#ifndef CW_RP
+#define CW_RP 1  // rounds of the compaction whose loads go before their stores (2 measured
+                 // the same, 4 lost occupancy)
+#endif
+static_assert(GJ_ROUNDS % CW_RP == 0, "whole groups of rounds");
 __device__ __forceinline__ void compact_write_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F,
                                                    const SPtrs& S, void* lds) {
   uint64_t* sh = reinterpret_cast<uint64_t*>(lds);
@@ -879,42 +884,73 @@ __device__ __forceinline__ void compact_write_body(const WorkItem w, const TDesc
   const int64_t base = (int64_t)w.tile * GJ_TILE;
   if (base >= M) return;
   uint64_t carry = F.agg[d.agg_off + w.tile];
-  for (int r = 0; r < GJ_ROUNDS; ++r) {
-    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
-    const int64_t se = d.off + e;
-    const bool ve = e < M, vg = e < G;
-    const bool es = ve && entry_survives(d, F, S, se);
-    const bool gs = vg && group_survives(d, S, se);
-    uint64_t tot;
-    const uint64_t ex = block_excl_sum((uint64_t)es | ((uint64_t)gs << 32), sh, tot) + carry;
-    carry += tot;
-    const int64_t ci = (int64_t)(uint32_t)ex;
-    const int64_t gi = (int64_t)(ex >> 32);
-    if (ve) {
-      S.e2c[se] = (int32_t)ci;
-      if (es) {
-        const int64_t sc = d.off + ci;
-        const uint64_t c = entry_count(F, se);
-        const uint64_t U = (uint64_t)S.U[se];
-        const uint64_t Dv = d.is_root ? 1ULL : (uint64_t)S.Dg[d.off + F.egrp[se]];
-        for (int k = 0; k < d.k; ++k)
-          S.ckey[d.key_off + (int64_t)k * d.n + ci] = F.ekey[d.key_off + (int64_t)k * d.n + e];
-        S.cc[sc] = (int64_t)c;
-        S.cU[sc] = (int64_t)U;
-        S.cD[sc] = (int64_t)Dv;
-        S.cF[sc] = (int64_t)smul(smul(c, U), Dv);
-        S.cpre[sc] = S.pre[se];
-        S.cstart[sc] = F.estart[se];
-        S.ccs[sc] = make_int2((int)c, F.estart[se]);
+  // CW_RP rounds at a time: every load of those rounds, then their prefix
+  // scans, then their stores (a wave's loads return only after its earlier
+  // stores)
+  for (int r0 = 0; r0 < GJ_ROUNDS; r0 += CW_RP) {
+    bool es[CW_RP], gs[CW_RP];
+    uint64_t c[CW_RP], U[CW_RP], Dv[CW_RP], pre[CW_RP], gM[CW_RP], gD[CW_RP];
+    int32_t est[CW_RP], gv[CW_RP];
+    int32_t key[CW_RP][MAXK];
+#pragma unroll
+    for (int u = 0; u < CW_RP; ++u) {
+      const int64_t e = base + (r0 + u) * GJ_BLOCK + threadIdx.x;
+      const int64_t se = d.off + e;
+      es[u] = e < M && entry_survives(d, F, S, se);
+      gs[u] = e < G && group_survives(d, S, se);
+      if (es[u]) {
+        c[u] = entry_count(F, se);
+        U[u] = (uint64_t)S.U[se];
+        Dv[u] = d.is_root ? 1ULL : (uint64_t)S.Dg[d.off + F.egrp[se]];
+        pre[u] = (uint64_t)S.pre[se];
+        est[u] = F.estart[se];
+#pragma unroll
+        for (int k = 0; k < MAXK; ++k)
+          if (k < d.k) key[u][k] = F.ekey[d.key_off + (int64_t)k * d.n + e];
+      }
+      if (gs[u]) {
+        gv[u] = F.gval[se];
+        gM[u] = (uint64_t)S.Mg[se];
+        gD[u] = d.is_root ? 1ULL : (uint64_t)S.Dg[se];
       }
     }
-    if (vg) {
-      S.g2c[se] = gs ? (int32_t)gi : -1;
-      if (gs) {
-        const int64_t sg = d.off + gi;
-        S.cgval[sg] = F.gval[se];
-        S.cgM[sg] = S.Mg[se];
-        S.cgD[sg] = d.is_root ? 1 : S.Dg[se];
+    int64_t ci[CW_RP], gi[CW_RP];
+#pragma unroll
+    for (int u = 0; u < CW_RP; ++u) {
+      uint64_t tot;
+      const uint64_t ex = block_excl_sum((uint64_t)es[u] | ((uint64_t)gs[u] << 32), sh, tot) + carry;
+      carry += tot;
+      ci[u] = (int64_t)(uint32_t)ex;
+      gi[u] = (int64_t)(ex >> 32);
+    }
+#pragma unroll
+    for (int u = 0; u < CW_RP; ++u) {
+      const int64_t e = base + (r0 + u) * GJ_BLOCK + threadIdx.x;
+      const int64_t se = d.off + e;
+      if (e < M) {
+        S.e2c[se] = (int32_t)ci[u];
+        if (es[u]) {
+          const int64_t sc = d.off + ci[u];
+#pragma unroll
+          for (int k = 0; k < MAXK; ++k)
+            if (k < d.k) S.ckey[d.key_off + (int64_t)k * d.n + ci[u]] = key[u][k];
+          S.cc[sc] = (int64_t)c[u];
+          S.cU[sc] = (int64_t)U[u];
+          S.cD[sc] = (int64_t)Dv[u];
+          S.cF[sc] = (int64_t)smul(smul(c[u], U[u]), Dv[u]);
+          S.cpre[sc] = (int64_t)pre[u];
+          S.cstart[sc] = est[u];
+          S.ccs[sc] = make_int2((int)c[u], est[u]);
+        }
+      }
+      if (e < G) {
+        S.g2c[se] = gs[u] ? (int32_t)gi[u] : -1;
+        if (gs[u]) {
+          const int64_t sg = d.off + gi[u];
+          S.cgval[sg] = gv[u];
+          S.cgM[sg] = (int64_t)gM[u];
+          S.cgD[sg] = (int64_t)gD[u];
+        }
       }
     }
   }
