@@ -293,6 +293,9 @@ __device__ __forceinline__ void runs_count_body(const WorkItem w, const TDesc* _
   if (threadIdx.x == 0) agg[d.agg_off + w.tile] = tot;
 }
 
+#ifndef RW_RP
+#define RW_RP 1  // rounds of the run writer whose loads go before their stores (2 and 4 slower)
+#endif
 template <int WIDE>
 __device__ __forceinline__ void runs_write_body(const WorkItem w, const TDesc* __restrict__ D, uint64_t* words0,
                                                 uint64_t* words1, const uint64_t* __restrict__ agg, const FPtrs& P,
@@ -305,45 +308,58 @@ __device__ __forceinline__ void runs_write_body(const WorkItem w, const TDesc* _
   const int64_t off = d.off;
   const uint64_t rbmask = d.rb == 0 ? 0ULL : ((1ULL << d.rb) - 1);
   uint64_t carry = agg[d.agg_off + w.tile];
-  for (int r = 0; r < GJ_ROUNDS; ++r) {
-    int64_t i = base + r * GJ_BLOCK + threadIdx.x;
-    bool valid = i < d.n;
-    bool h = false, s = false, nh = false, ns = false;
-    if (valid) {
-      run_flags<WIDE>(wv, d, i, h, s);
-      if (i + 1 == d.n) {
-        nh = true;
-        ns = true;
-      } else {
-        run_flags<WIDE>(wv, d, i + 1, nh, ns);
-        if (d.is_root) ns = false;
+  // RW_RP rounds at a time: their words and run flags first, then each
+  // round's scan and stores (a wave's loads return only after its earlier
+  // stores)
+  for (int r0 = 0; r0 < GJ_ROUNDS; r0 += RW_RP) {
+    typename WordT<WIDE>::type wd[RW_RP];
+    bool hv[RW_RP], sv[RW_RP], nhv[RW_RP], nsv[RW_RP];
+#pragma unroll
+    for (int u = 0; u < RW_RP; ++u) {
+      const int64_t i = base + (r0 + u) * GJ_BLOCK + threadIdx.x;
+      hv[u] = sv[u] = nhv[u] = nsv[u] = false;
+      if (i < d.n) {
+        run_flags<WIDE>(wv, d, i, hv[u], sv[u]);
+        if (i + 1 == d.n) {
+          nhv[u] = true;
+          nsv[u] = true;
+        } else {
+          run_flags<WIDE>(wv, d, i + 1, nhv[u], nsv[u]);
+          if (d.is_root) nsv[u] = false;
+        }
+        wd[u] = wv[i];
       }
     }
-    uint64_t v = (uint64_t)h | ((uint64_t)s << 32);
-    uint64_t tot;
-    uint64_t ex = block_excl_sum(v, sh, tot) + carry;
-    carry += tot;
-    if (!valid) continue;
-    const int64_t e = (int64_t)(uint32_t)ex + (h ? 0 : -1);
-    const int64_t g = (int64_t)(ex >> 32) + (s ? 0 : -1);
-    auto word = wv[i];
-    P.perm[off + i] = (int32_t)(wlow(word) & rbmask);
-    if (h) {
-      P.estart[off + e] = (int32_t)i;
-      P.egrp[off + e] = (int32_t)g;
-      for (int c = 0; c < d.k; ++c) {
-        uint32_t f = field_of(word, d.rb + d.fshift[c], d.fbits[c]);
-        P.ekey[d.key_off + (int64_t)c * d.n + e] = d.vmap[c] ? d.vmap[c][f] : (int32_t)(f + d.kmin[c]);
+#pragma unroll
+    for (int u = 0; u < RW_RP; ++u) {
+      const int64_t i = base + (r0 + u) * GJ_BLOCK + threadIdx.x;
+      const bool h = hv[u], s = sv[u];
+      uint64_t v = (uint64_t)h | ((uint64_t)s << 32);
+      uint64_t tot;
+      uint64_t ex = block_excl_sum(v, sh, tot) + carry;
+      carry += tot;
+      if (i >= d.n) continue;
+      const int64_t e = (int64_t)(uint32_t)ex + (h ? 0 : -1);
+      const int64_t g = (int64_t)(ex >> 32) + (s ? 0 : -1);
+      const auto word = wd[u];
+      P.perm[off + i] = (int32_t)(wlow(word) & rbmask);
+      if (h) {
+        P.estart[off + e] = (int32_t)i;
+        P.egrp[off + e] = (int32_t)g;
+        for (int c = 0; c < d.k; ++c) {
+          uint32_t f = field_of(word, d.rb + d.fshift[c], d.fbits[c]);
+          P.ekey[d.key_off + (int64_t)c * d.n + e] = d.vmap[c] ? d.vmap[c][f] : (int32_t)(f + d.kmin[c]);
+        }
       }
+      if (s) {
+        P.glo[off + g] = (int32_t)e;
+        int sc = d.is_root ? 0 : d.sep;
+        uint32_t f = field_of(word, d.rb + d.fshift[sc], d.fbits[sc]);
+        P.gval[off + g] = d.vmap[sc] ? d.vmap[sc][f] : (int32_t)(f + d.kmin[sc]);
+      }
+      if (nhv[u]) P.eend[off + e] = (int32_t)(i + 1);
+      if (nsv[u]) P.ghi[off + g] = (int32_t)(e + 1);
     }
-    if (s) {
-      P.glo[off + g] = (int32_t)e;
-      int sc = d.is_root ? 0 : d.sep;
-      uint32_t f = field_of(word, d.rb + d.fshift[sc], d.fbits[sc]);
-      P.gval[off + g] = d.vmap[sc] ? d.vmap[sc][f] : (int32_t)(f + d.kmin[sc]);
-    }
-    if (nh) P.eend[off + e] = (int32_t)(i + 1);
-    if (ns) P.ghi[off + g] = (int32_t)(e + 1);
   }
 }
 
@@ -517,6 +533,9 @@ __device__ __forceinline__ void seg_tiles_body(int t, const TDesc* __restrict__ 
 
 // Exclusive prefix of c*U inside each separator group (the block offsets of
 // desummarization), the group totals M, and the root's join size.
+#ifndef US_RP
+#define US_RP 1  // rounds of the upward scan whose loads go before their stores (4 slower)
+#endif
 __device__ __forceinline__ void up_scan_body(const WorkItem w, const TDesc* __restrict__ D, const FPtrs& F,
                                              const SPtrs& S, void* lds) {
   uint64_t* shv = reinterpret_cast<uint64_t*>(lds);
@@ -527,39 +546,53 @@ __device__ __forceinline__ void up_scan_body(const WorkItem w, const TDesc* __re
   const int64_t base = (int64_t)w.tile * GJ_TILE;
   if (base >= M) return;
   uint64_t cv = F.agg[d.agg_off + w.tile];
-  for (int r = 0; r < GJ_ROUNDS; ++r) {
-    const int64_t e = base + r * GJ_BLOCK + threadIdx.x;
-    const int64_t se = d.off + e;
-    uint64_t cu = 0;
-    uint32_t head = 0;
-    const bool valid = e < M;
-    if (valid) {
-      const uint64_t c = entry_count(F, se);
-      cu = smul(c, (uint64_t)S.U[se]);
-      head = (e == 0 || F.egrp[se] != F.egrp[se - 1]) ? 1u : 0u;
-    }
-    uint64_t v = cu;
-    uint32_t f = head;
-    uint64_t tv;
-    uint32_t tf;
-    block_seg_incl(v, f, shv, shf, tv, tf);
-    const uint64_t mine = f ? v : sadd(cv, v);
-    incl[threadIdx.x] = mine;
-    __syncthreads();
-    if (valid) {
-      const uint64_t ex = head ? 0ULL : (threadIdx.x == 0 ? cv : incl[threadIdx.x - 1]);
-      S.pre[se] = (int64_t)ex;
-      const bool last = (e + 1 == M) || F.egrp[se + 1] != F.egrp[se];
-      if (last) {
-        S.Mg[d.off + F.egrp[se]] = (int64_t)mine;
-        if (d.is_root) {
-          S.qsize[d.query] = (int64_t)mine;
-          S.qstatus[d.query] = mine >= SATV ? GJ_E_OVERFLOW : GJ_OK;
-        }
+  // US_RP rounds at a time: their loads first, then each round's scan and
+  // stores (a wave's loads return only after its earlier stores)
+  for (int r0 = 0; r0 < GJ_ROUNDS; r0 += US_RP) {
+    uint64_t cuv[US_RP];
+    uint32_t hd[US_RP], lst[US_RP];
+    int32_t grp[US_RP];
+#pragma unroll
+    for (int u = 0; u < US_RP; ++u) {
+      const int64_t e = base + (r0 + u) * GJ_BLOCK + threadIdx.x;
+      const int64_t se = d.off + e;
+      cuv[u] = 0;
+      hd[u] = 0;
+      lst[u] = 0;
+      grp[u] = 0;
+      if (e < M) {
+        cuv[u] = smul(entry_count(F, se), (uint64_t)S.U[se]);
+        grp[u] = F.egrp[se];
+        hd[u] = (e == 0 || grp[u] != F.egrp[se - 1]) ? 1u : 0u;
+        lst[u] = ((e + 1 == M) || F.egrp[se + 1] != grp[u]) ? 1u : 0u;
       }
     }
-    cv = incl[GJ_BLOCK - 1];
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < US_RP; ++u) {
+      const int64_t e = base + (r0 + u) * GJ_BLOCK + threadIdx.x;
+      const int64_t se = d.off + e;
+      uint64_t v = cuv[u];
+      uint32_t f = hd[u];
+      uint64_t tv;
+      uint32_t tf;
+      block_seg_incl(v, f, shv, shf, tv, tf);
+      const uint64_t mine = f ? v : sadd(cv, v);
+      incl[threadIdx.x] = mine;
+      __syncthreads();
+      if (e < M) {
+        const uint64_t ex = hd[u] ? 0ULL : (threadIdx.x == 0 ? cv : incl[threadIdx.x - 1]);
+        S.pre[se] = (int64_t)ex;
+        if (lst[u]) {
+          S.Mg[d.off + grp[u]] = (int64_t)mine;
+          if (d.is_root) {
+            S.qsize[d.query] = (int64_t)mine;
+            S.qstatus[d.query] = mine >= SATV ? GJ_E_OVERFLOW : GJ_OK;
+          }
+        }
+      }
+      cv = incl[GJ_BLOCK - 1];
+      __syncthreads();
+    }
   }
 }
 
