@@ -462,7 +462,10 @@ __device__ __forceinline__ void up_agg_body(const WorkItem w, const TDesc* __res
               j = find_sorted(F.gval + dc.off, F.cnt[ch * CNT_STRIDE + CNT_G], v);
             }
             S.link[dc.link_off + e] = j;
-            const uint64_t m = j >= 0 ? (uint64_t)S.Mg[dc.off + j] : 0ULL;
+            // a leaf with one row per group (a key column such as a primary
+            // key) sends 1 from every group: c = 1 and U = 1
+            const bool unit = dc.nchild == 0 && F.ecnt == nullptr && F.cnt[ch * CNT_STRIDE + CNT_G] == dc.n;
+            const uint64_t m = j < 0 ? 0ULL : unit ? 1ULL : (uint64_t)S.Mg[dc.off + j];
             mi[i] = m;
             U = smul(U, m);
           }
