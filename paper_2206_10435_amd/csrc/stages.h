@@ -1041,13 +1041,21 @@ __device__ __forceinline__ void compact_links_body(const WorkItem w, const TDesc
     const int4* grec = reinterpret_cast<const int4*>(S.grec + dc.off);
     int4* crec = reinterpret_cast<int4*>(S.crec + dc.link_off);
     const int32_t* link = S.link + dc.link_off + base + threadIdx.x;
+    // a leaf with one row per group all of whose entries survive: group g is
+    // entry g, of one row, at perm position g -- its record needs no gather
+    const int ch = d.child[i];
+    const bool unit = dc.nchild == 0 && F.ecnt == nullptr && F.cnt[ch * CNT_STRIDE + CNT_G] == dc.n &&
+                      F.cnt[ch * CNT_STRIDE + CNT_MC] == dc.n;
     int4 rec[GJ_ROUNDS];
 #pragma unroll
     for (int r = 0; r < GJ_ROUNDS; ++r) {
       // a surviving entry's child group survives (its message and its
       // downward message are both > 0)
       rec[r] = make_int4(0, 0, 0, 0);
-      if (ci[r] >= 0) rec[r] = grec[link[r * GJ_BLOCK]];
+      if (ci[r] >= 0) {
+        const int32_t g = link[r * GJ_BLOCK];
+        rec[r] = unit ? make_int4(g, g + 1, 1, g) : grec[g];
+      }
     }
 #pragma unroll
     for (int r = 0; r < GJ_ROUNDS; ++r)

@@ -363,3 +363,55 @@ def test_block_offsets_beyond_32_bits(gctx, oracle_mod):
                 assert np.array_equal(got[i], o.unrank(first + i)), (general, i)
     finally:
         gctx.set_tune()
+
+
+def _unique_leaves(seed, fact, dims, all_referenced):
+    """Fact F(k1..kd) into dimensions D_i(pk), pk a permutation (one row per
+    group): every dimension row referenced, or only the first half of each
+    dimension's keys."""
+    rng = np.random.default_rng(seed)
+    fcols = []
+    for nd in dims:
+        if all_referenced:
+            c = np.concatenate([np.arange(nd), rng.integers(0, nd, size=fact - nd)])
+            rng.shuffle(c)
+        else:
+            c = rng.integers(0, nd // 2, size=fact)
+        fcols.append(c.astype(np.int32))
+    tables = [fcols] + [[rng.permutation(nd).astype(np.int32)] for nd in dims]
+    n = len(dims)
+    name = "unique_leaves_" + ("all" if all_referenced else "half")
+    return W.Query(name, tables, [-1] + [0] * n, [0] * (n + 1), [0] + list(range(n)))
+
+
+@pytest.mark.parametrize("all_referenced", [True, False], ids=["all_rows_referenced", "half_unreferenced"])
+def test_unique_key_leaves(gctx, oracle_mod, all_referenced):
+    """Leaves keyed by a unique column send 1 from every group (the upward pass
+    gathers no message from them) and, when every row survives, get their child
+    records without a gather; with unreferenced rows the records are gathered.
+    The summary and every tuple, by both expansion kernels, against the oracle."""
+    import torch
+
+    from paper_2206_10435_amd import gj
+
+    q = _unique_leaves(31, 20_000, (700, 1500, 3000), all_referenced)
+    o = oracle_mod.Oracle(q)
+    Q, ovf = o.join_size()
+    assert not ovf and Q == 20_000
+    _say("case", q.name, "Q =", Q)
+    s = gctx.summarize(gctx.build_factors(gj.to_device_tables(q), q.parent, q.sep_col, q.parent_col))
+    assert s.join_size == Q
+    for t in range(q.n_tables):
+        g, r = s.table(t), o.summary_table(t)
+        for k in ("keys", "c", "U", "D", "F"):
+            assert np.array_equal(g[k], r[k]), (t, k)
+    ref = o.canonical_result().astype(np.int64)
+    try:
+        for general in (0, 1):
+            gctx.set_tune(desum_general=general)
+            got = _desum(gctx, s, q.n_tables, 0, Q, torch.int64)
+            assert np.array_equal(got, ref), general
+            got = _desum(gctx, s, q.n_tables, 777, 5000, torch.int32)
+            assert np.array_equal(got, ref[777:5777]), general
+    finally:
+        gctx.set_tune()
