@@ -423,6 +423,12 @@ __device__ __forceinline__ int32_t find_sorted(const int32_t* __restrict__ a, in
   return (lo < n && a[lo] == v) ? (int32_t)lo : -1;
 }
 
+// A leaf with one row per group (a key column such as a primary key, with the
+// rows' own counts): every group sends 1 (c = 1, U = 1).
+__device__ __forceinline__ bool unit_leaf(const TDesc* __restrict__ D, const FPtrs& F, int ch) {
+  return D[ch].nchild == 0 && F.ecnt == nullptr && F.cnt[ch * CNT_STRIDE + CNT_G] == D[ch].n;
+}
+
 // U per entry of tile w (looking each child value up in the child's group
 // index or its sorted separator values, which also records the entry ->
 // child-group link), and the tile aggregate of a segmented scan of c*U.
@@ -462,17 +468,15 @@ __device__ __forceinline__ void up_agg_body(const WorkItem w, const TDesc* __res
               j = find_sorted(F.gval + dc.off, F.cnt[ch * CNT_STRIDE + CNT_G], v);
             }
             S.link[dc.link_off + e] = j;
-            // a leaf with one row per group (a key column such as a primary
-            // key) sends 1 from every group: c = 1 and U = 1
-            const bool unit = dc.nchild == 0 && F.ecnt == nullptr && F.cnt[ch * CNT_STRIDE + CNT_G] == dc.n;
-            const uint64_t m = j < 0 ? 0ULL : unit ? 1ULL : (uint64_t)S.Mg[dc.off + j];
+            const uint64_t m = j < 0 ? 0ULL : unit_leaf(D, F, ch) ? 1ULL : (uint64_t)S.Mg[dc.off + j];
             mi[i] = m;
             U = smul(U, m);
           }
         }
         // each child's product of the other children's messages, for the
         // children summed by buckets in the downward pass (it multiplies the
-        // product in instead of gathering the messages again)
+        // product in instead of gathering the messages again); for a unit
+        // leaf it is U itself, which that pass reads instead
         {
           uint64_t pre = 1;
 #pragma unroll
@@ -482,7 +486,8 @@ __device__ __forceinline__ void up_agg_body(const WorkItem w, const TDesc* __res
 #pragma unroll
               for (int i2 = i + 1; i2 < MAXC; ++i2)
                 if (i2 < d.nchild) x = smul(x, mi[i2]);
-              if (D[d.child[i]].dbucketed) S.xprod[D[d.child[i]].link_off + e] = (int64_t)x;
+              if (D[d.child[i]].dbucketed && !unit_leaf(D, F, d.child[i]))
+                S.xprod[D[d.child[i]].link_off + e] = (int64_t)x;
               pre = smul(pre, mi[i]);
             }
           }
@@ -736,6 +741,7 @@ __device__ __forceinline__ void down_tile_body(const WorkItem w, const TDesc* __
     cnt[tid] = 0;
     // every load of this child first (a wave's loads return only after its
     // earlier stores): links and products into registers, the stores last
+    const bool unit = unit_leaf(D, F, ch);  // the product of the other messages is U
     int32_t jv[GJ_ROUNDS];
     uint64_t xv[GJ_ROUNDS];
 #pragma unroll
@@ -745,7 +751,7 @@ __device__ __forceinline__ void down_tile_body(const WorkItem w, const TDesc* __
       xv[r] = 0;
       if (e < M) {
         jv[r] = link[e];
-        xv[r] = (uint64_t)S.xprod[dc.link_off + e];
+        xv[r] = unit ? (uint64_t)S.U[d.off + e] : (uint64_t)S.xprod[dc.link_off + e];
       }
     }
     __syncthreads();
@@ -1044,8 +1050,7 @@ __device__ __forceinline__ void compact_links_body(const WorkItem w, const TDesc
     // a leaf with one row per group all of whose entries survive: group g is
     // entry g, of one row, at perm position g -- its record needs no gather
     const int ch = d.child[i];
-    const bool unit = dc.nchild == 0 && F.ecnt == nullptr && F.cnt[ch * CNT_STRIDE + CNT_G] == dc.n &&
-                      F.cnt[ch * CNT_STRIDE + CNT_MC] == dc.n;
+    const bool unit = unit_leaf(D, F, ch) && F.cnt[ch * CNT_STRIDE + CNT_MC] == dc.n;
     int4 rec[GJ_ROUNDS];
 #pragma unroll
     for (int r = 0; r < GJ_ROUNDS; ++r) {
