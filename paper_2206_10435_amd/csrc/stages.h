@@ -495,7 +495,13 @@ __device__ __forceinline__ void up_agg_body(const WorkItem w, const TDesc* __res
         const uint64_t c = entry_count(F, se);
         cu = smul(c, U);
         S.U[se] = (int64_t)U;
-        head = (e == 0 || F.egrp[se] != F.egrp[se - 1]) ? 1u : 0u;
+        if (!d.is_root) head = (e == 0 || F.egrp[se] != F.egrp[se - 1]) ? 1u : 0u;
+      }
+      if (d.is_root) {
+        // the root is one group: its tile aggregate is a plain (saturating)
+        // sum, kept per thread and reduced once below
+        av = sadd(av, cu);
+        continue;
       }
       uint64_t tv;
       uint32_t tf;
@@ -503,6 +509,16 @@ __device__ __forceinline__ void up_agg_body(const WorkItem w, const TDesc* __res
       av = tf ? tv : sadd(av, tv);
       af |= tf;
     }
+  }
+  if (d.is_root) {  // uniform
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) av = sadd(av, (uint64_t)__shfl_xor((long long)av, o, 64));
+    if (lane_id() == 0) shv[wave_id()] = av;
+    __syncthreads();
+    av = 0;
+#pragma unroll
+    for (int v = 0; v < GJ_WAVES; ++v) av = sadd(av, shv[v]);
+    af = (w.tile == 0 && M > 0) ? 1u : 0u;  // the head of the root's one group is entry 0
   }
   if (threadIdx.x == 0) {
     F.agg[d.agg_off + w.tile] = av;
