@@ -561,7 +561,8 @@ static void launch_sort(const Plan& P, const FPtrs& F, hipStream_t s) {
   for (int p = 0; p < P.max_passes; ++p)
     for (int w = 0; w < 2; ++w) {
       const WL& l = P.sort[w][p];
-      gjk::radix_pass(s, w, P.sort_items[w], P.d_wl + l.off, l.n, P.d_tabs + l.toff, l.tn, P.d_desc, F, p);
+      // the pack counted the first pass's digits
+      gjk::radix_pass(s, w, P.sort_items[w], P.d_wl + l.off, l.n, P.d_tabs + l.toff, l.tn, P.d_desc, F, p, p > 0);
     }
   if (P.local.n > 0) {
     gjk::fill_i32(s, F.lflag, P.nt, 0, 0);

@@ -69,9 +69,9 @@ __device__ __forceinline__ void run_unit(const PArgs& a, const PStage& st, int u
     }
     case gjk::PK_PACK:
       if (D[st.t].wide)
-        pack_body<1>(w, D, F.words[0]);
+        pack_body<1>(w, D, F.words[0], F.hist, lds);
       else
-        pack_body<0>(w, D, F.words[0]);
+        pack_body<0>(w, D, F.words[0], F.hist, lds);
       break;
     case gjk::PK_UP:
       if (D[st.t].wide)
@@ -217,6 +217,7 @@ namespace gjk {
 size_t persistent_lds(int sort_items64) {
   size_t m = std::max<size_t>(LDS_DOWN, LDS_SEG);
   m = std::max<size_t>(m, LDS_UPSWEEP);
+  m = std::max<size_t>(m, LDS_PACK);
   m = std::max<size_t>(m, lds_downsweep<1, 8>());
   m = std::max<size_t>(m, sort_items64 == 16 ? lds_downsweep<0, 16>() : lds_downsweep<0, 8>());
   return m;

@@ -106,8 +106,9 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v0, int32_t v1) {
 // ---------------------------------------------------------------------------
 template <int WIDE>
 __global__ void __launch_bounds__(GJ_BLOCK) k_pack(const WorkItem* __restrict__ wl, const TDesc* __restrict__ D,
-                                                   uint64_t* __restrict__ words0) {
-  pack_body<WIDE>(wl[blockIdx.x], D, words0);
+                                                   uint64_t* __restrict__ words0, uint32_t* __restrict__ hist) {
+  __shared__ __align__(16) unsigned char lds[LDS_PACK];
+  pack_body<WIDE>(wl[blockIdx.x], D, words0, hist, lds);
 }
 
 template <int WIDE, int ITEMS>
@@ -220,18 +221,19 @@ void minmax(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int
 void pack(hipStream_t s, int wide, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& P) {
   if (nwl <= 0) return;
   if (wide)
-    hipLaunchKernelGGL(k_pack<1>, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, P.words[0]);
+    hipLaunchKernelGGL(k_pack<1>, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, P.words[0], P.hist);
   else
-    hipLaunchKernelGGL(k_pack<0>, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, P.words[0]);
+    hipLaunchKernelGGL(k_pack<0>, dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, P.words[0], P.hist);
 }
 
 void radix_pass(hipStream_t s, int wide, int items, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab,
-                const TDesc* D, const FPtrs& P, int pass) {
+                const TDesc* D, const FPtrs& P, int pass, bool upsweep) {
   if (nwl <= 0) return;
 #define GJ_RADIX_CASE(W, I)                                                                                        \
   if (wide == W && items == I) {                                                                                   \
-    hipLaunchKernelGGL((k_upsweep<W, I>), dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, P.words[0], P.words[1], P.hist, \
-                       pass);                                                                                      \
+    if (upsweep)                                                                                                   \
+      hipLaunchKernelGGL((k_upsweep<W, I>), dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, P.words[0], P.words[1],      \
+                         P.hist, pass);                                                                            \
     hipLaunchKernelGGL(k_digit_scan, dim3(ntab * 256), dim3(GJ_BLOCK), 0, s, tabs, D, P.hist, P.dtot);            \
     hipLaunchKernelGGL((k_downsweep<W, I>), dim3(nwl), dim3(GJ_BLOCK), 0, s, wl, D, P.words[0], P.words[1],       \
                        P.hist, P.dtot, pass);                                                                      \

@@ -13,8 +13,10 @@ void minmax(hipStream_t s, const WorkItem* wl, int nwl, const int32_t* tabs, int
 void pack(hipStream_t s, int wide, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& P);
 // rank[perm[i]] = entry of position i of a one-column factor (m entries, n rows).
 void rank_rows(hipStream_t s, const int32_t* perm, const int32_t* estart, int64_t m, int64_t n, int32_t* rank);
+// one LSD pass; upsweep = false when the digit counts are already in P.hist
+// (the pack writes the first pass's)
 void radix_pass(hipStream_t s, int wide, int items, const WorkItem* wl, int nwl, const int32_t* tabs, int ntab,
-                const TDesc* D, const FPtrs& P, int pass);
+                const TDesc* D, const FPtrs& P, int pass, bool upsweep = true);
 // sort_local.hip: the buckets of tables with `local` set, sorted in LDS
 // (words[0] -> words[1]); lflag[t] = 1 where a bucket is too long
 void local_sort(hipStream_t s, const WorkItem* wl, int nwl, const TDesc* D, const FPtrs& F);

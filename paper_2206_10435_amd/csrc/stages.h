@@ -86,13 +86,25 @@ constexpr int LDS_DOWN = DOWN_HASH * 4 + DOWN_HASH * 8;
 // factor build
 // ---------------------------------------------------------------------------
 
-// One sort word per row of tile w: key fields above the row id.
+// One sort word per row of tile w: key fields above the row id.  It also
+// counts the first radix pass's digits of every sort tile it covers (the
+// counts that pass's upsweep would read the words again for).
+constexpr int LDS_PACK = 2 * 256 * 4;  // a pack tile covers at most two sort tiles
 template <int WIDE>
-__device__ __forceinline__ void pack_body(const WorkItem w, const TDesc* __restrict__ D, uint64_t* __restrict__ words0) {
+__device__ __forceinline__ void pack_body(const WorkItem w, const TDesc* __restrict__ D, uint64_t* __restrict__ words0,
+                                          uint32_t* __restrict__ hist, void* lds) {
+  uint32_t* h = reinterpret_cast<uint32_t*>(lds);
   const TDesc& d = D[w.t];
   if (d.wide != WIDE) return;
   auto* out = word_ptr<WIDE>(words0, d);
   const int64_t base = (int64_t)w.tile * GJ_TILE;
+  const bool count = d.npasses > 0;
+  const int nd = 1 << d.dbits;
+  const uint32_t mask = (uint32_t)nd - 1;
+  if (count) {
+    for (int i = threadIdx.x; i < 2 * 256; i += GJ_BLOCK) h[i] = 0;
+    __syncthreads();
+  }
   for (int r = 0; r < GJ_ROUNDS; ++r) {
     int64_t i = base + r * GJ_BLOCK + threadIdx.x;
     if (i >= d.n) break;
@@ -115,9 +127,21 @@ __device__ __forceinline__ void pack_body(const WorkItem w, const TDesc* __restr
       }
     }
     if constexpr (WIDE) {
-      out[i] = W128{lo, hi};
+      const W128 word{lo, hi};
+      out[i] = word;
+      if (count) atomicAdd(&h[((i - base) / d.sort_tile) * 256 + digit_of(word, d.sh0, mask)], 1u);
     } else {
       out[i] = lo;
+      if (count) atomicAdd(&h[((i - base) / d.sort_tile) * 256 + digit_of(lo, d.sh0, mask)], 1u);
+    }
+  }
+  if (count) {
+    __syncthreads();
+    const int nst = GJ_TILE / d.sort_tile;
+    const int64_t st0 = base / d.sort_tile;
+    for (int k = threadIdx.x; k < nst * nd; k += GJ_BLOCK) {
+      const int64_t st = st0 + k / nd;
+      if (st < d.ntiles_sort) hist[d.hist_off + (int64_t)(k % nd) * d.ntiles_sort + st] = h[(k / nd) * 256 + k % nd];
     }
   }
 }
