@@ -31,9 +31,10 @@
 namespace {
 
 // 512 threads and one 1920-word buffer (40 KB of LDS with the histograms):
-// four blocks share a CU (two 4096-word buffers and 1024 threads, one block a
-// CU, ran 2.5 times longer).  With tiles of 704 positions a bucket of up to
-// 1216 words fits wherever it starts.
+// four blocks share a CU.  (A first form -- 1024 threads, two 4096-word
+// buffers, one block a CU, eight LSD passes -- took 3.6 ms for 5e7 words,
+// against 0.87 ms for this one.)  With tiles of 704 positions a bucket of up
+// to 1216 words fits wherever it starts.
 constexpr int LS_BLOCK = 512;
 constexpr int LS_CAP = 1920;  // longest range a block sorts
 constexpr int LS_WAVES = LS_BLOCK / 64;
