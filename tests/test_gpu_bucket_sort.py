@@ -125,3 +125,21 @@ def test_same_factors_as_the_per_digit_sort(gctx):
                 assert np.array_equal(g[k], ref[t][k]), (t, k)
     finally:
         gctx.set_tune(sort_local_rows=1)
+
+
+def test_bad_arguments_refused(gctx):
+    """sort_local_rows < 0 and a table index outside the factor set are refused
+    with GJ_E_INVALID, and the context keeps its setting."""
+    from paper_2206_10435_amd import gj
+
+    with pytest.raises(gj.GJError) as ei:
+        gctx.set_tune(sort_local_rows=-1)
+    assert ei.value.status == gj.GJ_E_INVALID
+    assert b"sort_local_rows" in gj.load_library().gj_last_error(gctx.h)
+    name, q = _cases()[5]  # two tables of 1 and 50 rows
+    f = gctx.build_factors(gj.to_device_tables(q), q.parent, q.sep_col, q.parent_col)
+    for t in (-1, q.n_tables):
+        with pytest.raises(gj.GJError) as ei:
+            f.sort_kind(t)
+        assert ei.value.status == gj.GJ_E_INVALID
+    assert f.sort_kind(1) == "digits"
